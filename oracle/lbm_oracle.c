@@ -1,0 +1,416 @@
+/*
+ * FP64 CPU oracle for the D2Q9 BGK cylinder-flow method (arXiv 2605.02185).
+ * TEST INFRASTRUCTURE ONLY: see lbm_oracle.h.  Built with gcc; never linked
+ * into the GPU library.
+ *
+ * One time step, in the paper's order (Sec. 2.1, last paragraph):
+ *   O1 collide every fluid node (Eqs. 2-4)
+ *   O2 momentum-exchange force from the post-collision populations (Eq. 14)
+ *   O3 push-stream; a population that would enter a solid node is flipped
+ *      back into the opposite direction of its own node in the same step
+ *      (half-way bounce-back, Sec. 3.1)
+ *   O4 top and bottom rows (Sec. 2.3.1-2.3.4)
+ *   O5 outlet column, zeroth-order extrapolation (Eq. 13)
+ *   O6 velocity inlet column, Zou-He (Sec. 3.1)
+ *   O7 inlet corners
+ *   O8 the corrected populations become the new state
+ * Targets that nothing writes in O3 are the populations missing at the domain
+ * edges (Fig. 2); they are set to NaN before streaming so that a boundary pass
+ * that forgets one is caught by the finiteness check below.
+ */
+#include "lbm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Table 1 with k = i - 1. */
+static const int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const double W[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+/* opposite direction: c_opp(k) = -c_k */
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+enum { R = 0, E = 1, N = 2, Wd = 3, S = 4, NE = 5, NW = 6, SW = 7, SE = 8 };
+
+struct oracle {
+  oracle_params p;
+  int nx, ny;
+  double tau;
+  double u_top, u_bot;
+  unsigned char* solid; /* [ny][nx] */
+  double* f;            /* state f(t), [ny][nx][9] */
+  double* fs;           /* post-collision f*(t) */
+  double* g;            /* streamed populations f(t+1) under construction */
+  double* rho_t;        /* density of f(t) per node, used by Eq. 11 */
+  int state_is_post;    /* 1: f holds f*(t) (set by oracle_set_fstar) */
+  long t;
+};
+
+static size_t node(const oracle* o, int x, int y) { return (size_t)y * o->nx + x; }
+
+/* Eq. 3 with c = 1: f_eq_k = w_k rho [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u] */
+static double feq(int k, double rho, double ux, double uy) {
+  double cu = CX[k] * ux + CY[k] * uy;
+  double uu = ux * ux + uy * uy;
+  return W[k] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+}
+
+double oracle_tau(const oracle_params* p) {
+  if (p->tau > 0) return p->tau;
+  double nu = p->u_in * p->diameter / p->re; /* Eq. 16 */
+  return 3.0 * nu + 0.5;                     /* Eq. 17 */
+}
+
+long oracle_digitise(const oracle_params* p, unsigned char* solid) {
+  long count = 0;
+  long d2 = (long)p->diameter * p->diameter;
+  for (int y = 0; y < p->ny; ++y)
+    for (int x = 0; x < p->nx; ++x) {
+      long dx = 2L * x - p->cx2, dy = 2L * y - p->cy2;
+      int s = p->diameter > 0 && dx * dx + dy * dy <= d2;
+      solid[(size_t)y * p->nx + x] = (unsigned char)s;
+      count += s;
+    }
+  return count;
+}
+
+static void init_equilibrium(oracle* o) {
+  const double U = o->p.u_in, a = o->p.perturb_amp;
+  const double pi = 3.14159265358979323846;
+  for (int y = 0; y < o->ny; ++y) {
+    double v = o->ny > 1 ? a * U * sin(2.0 * pi * y / (o->ny - 1)) : 0.0;
+    for (int x = 0; x < o->nx; ++x)
+      for (int k = 0; k < 9; ++k) o->f[node(o, x, y) * 9 + k] = feq(k, 1.0, U, v);
+  }
+}
+
+oracle* oracle_create(const oracle_params* p, const unsigned char* solid) {
+  if (!p || p->nx < 3 || p->ny < 3) return NULL;
+  oracle* o = (oracle*)calloc(1, sizeof(oracle));
+  if (!o) return NULL;
+  o->p = *p;
+  o->nx = p->nx;
+  o->ny = p->ny;
+  o->tau = oracle_tau(p);
+  o->u_top = isnan(p->u_wall_top) ? p->u_in : p->u_wall_top;
+  o->u_bot = isnan(p->u_wall_bottom) ? p->u_in : p->u_wall_bottom;
+  size_t nn = (size_t)o->nx * o->ny;
+  o->solid = (unsigned char*)malloc(nn);
+  o->f = (double*)malloc(nn * 9 * sizeof(double));
+  o->fs = (double*)malloc(nn * 9 * sizeof(double));
+  o->g = (double*)malloc(nn * 9 * sizeof(double));
+  o->rho_t = (double*)malloc(nn * sizeof(double));
+  if (!o->solid || !o->f || !o->fs || !o->g || !o->rho_t) {
+    oracle_destroy(o);
+    return NULL;
+  }
+  if (solid)
+    memcpy(o->solid, solid, nn);
+  else
+    oracle_digitise(p, o->solid);
+  init_equilibrium(o);
+  return o;
+}
+
+void oracle_destroy(oracle* o) {
+  if (!o) return;
+  free(o->solid);
+  free(o->f);
+  free(o->fs);
+  free(o->g);
+  free(o->rho_t);
+  free(o);
+}
+
+long oracle_time(const oracle* o) { return o->t; }
+
+/* Moments of Eq. 4 at one node; with a body force the velocity is shifted by
+ * half the force (Guo et al. 2002), which only the test boxes use. */
+static void moments(const oracle* o, const double* fn, double* rho, double* ux, double* uy) {
+  double r = 0, mx = 0, my = 0;
+  for (int k = 0; k < 9; ++k) {
+    r += fn[k];
+    mx += CX[k] * fn[k];
+    my += CY[k] * fn[k];
+  }
+  *rho = r;
+  *ux = (mx + 0.5 * r * o->p.gx) / r;
+  *uy = (my + 0.5 * r * o->p.gy) / r;
+}
+
+/* O1: BGK collision f* = f - (f - f_eq)/tau (Eq. 2).  Returns 1 if some fluid
+ * density is non-finite or outside (0, 10). */
+static int collide(oracle* o) {
+  int bad = 0;
+  const double tau = o->tau;
+  const int forced = o->p.gx != 0.0 || o->p.gy != 0.0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+  for (int y = 0; y < o->ny; ++y) {
+    for (int x = 0; x < o->nx; ++x) {
+      size_t n = node(o, x, y);
+      const double* fn = o->f + n * 9;
+      double* out = o->fs + n * 9;
+      if (o->solid[n]) {
+        for (int k = 0; k < 9; ++k) out[k] = fn[k];
+        o->rho_t[n] = 1.0;
+        continue;
+      }
+      double rho, ux, uy;
+      moments(o, fn, &rho, &ux, &uy);
+      o->rho_t[n] = rho;
+      if (!(rho > 0.0 && rho < 10.0)) bad = 1;
+      if (o->state_is_post) {
+        for (int k = 0; k < 9; ++k) out[k] = fn[k];
+        continue;
+      }
+      for (int k = 0; k < 9; ++k) {
+        double fk = fn[k];
+        out[k] = fk - (fk - feq(k, rho, ux, uy)) / tau;
+        if (forced) {
+          /* Guo source term, test boxes only */
+          double cu = CX[k] * ux + CY[k] * uy;
+          double fx = rho * o->p.gx, fy = rho * o->p.gy;
+          double src = W[k] * (3.0 * ((CX[k] - ux) * fx + (CY[k] - uy) * fy) + 9.0 * cu * (CX[k] * fx + CY[k] * fy));
+          out[k] += (1.0 - 0.5 / tau) * src;
+        }
+      }
+    }
+  }
+  o->state_is_post = 0;
+  return bad;
+}
+
+/* Neighbour of (x, y) along c_k.  Wraps in y for periodic walls and in x for
+ * periodic test boxes.  Returns 0 if it falls outside the lattice. */
+static int neighbour(const oracle* o, int x, int y, int k, int* xo, int* yo) {
+  int xn = x + CX[k], yn = y + CY[k];
+  if (o->p.x_periodic) xn = (xn + o->nx) % o->nx;
+  if (o->p.wall == ORACLE_WALL_PERIODIC) yn = (yn + o->ny) % o->ny;
+  if (xn < 0 || xn >= o->nx || yn < 0 || yn >= o->ny) return 0;
+  *xo = xn;
+  *yo = yn;
+  return 1;
+}
+
+/* O2: Eq. 14 summed over every link from a fluid node into a solid node, all
+ * eight directions.  The population leaving along c_k is f*_k, the one coming
+ * back along -c_k has the same value (stationary wall, same step), so the
+ * momentum given to the body per link is 2 c_k f*_k. */
+static void force(const oracle* o, double* fx, double* fy) {
+  double sx = 0.0, sy = 0.0;
+  for (int y = 0; y < o->ny; ++y)
+    for (int x = 0; x < o->nx; ++x) {
+      size_t n = node(o, x, y);
+      if (o->solid[n]) continue;
+      for (int k = 1; k < 9; ++k) {
+        int xn, yn;
+        if (!neighbour(o, x, y, k, &xn, &yn)) continue;
+        if (!o->solid[node(o, xn, yn)]) continue;
+        sx += 2.0 * CX[k] * o->fs[n * 9 + k];
+        sy += 2.0 * CY[k] * o->fs[n * 9 + k];
+      }
+    }
+  *fx = sx;
+  *fy = sy;
+}
+
+/* O3: push streaming with half-way bounce-back at solid nodes. */
+static void stream(oracle* o) {
+  size_t total = (size_t)o->nx * o->ny * 9;
+  for (size_t i = 0; i < total; ++i) o->g[i] = NAN;
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < o->ny; ++y)
+    for (int x = 0; x < o->nx; ++x) {
+      size_t n = node(o, x, y);
+      if (o->solid[n]) continue;
+      for (int k = 0; k < 9; ++k) {
+        int xn, yn;
+        if (!neighbour(o, x, y, k, &xn, &yn)) continue; /* leaves the lattice */
+        size_t m = node(o, xn, yn);
+        if (o->solid[m])
+          o->g[n * 9 + OPP[k]] = o->fs[n * 9 + k];
+        else
+          o->g[m * 9 + k] = o->fs[n * 9 + k];
+      }
+    }
+}
+
+/* O4: the top row (y = ny-1) is missing S, SW, SE; the bottom row (y = 0) is
+ * missing N, NE, NW (Fig. 2). */
+static void walls(oracle* o) {
+  if (o->p.wall == ORACLE_WALL_PERIODIC) return;
+  int x0 = o->p.x_periodic ? 0 : 1;
+  int x1 = o->p.x_periodic ? o->nx - 1 : o->nx - 2;
+  for (int x = x0; x <= x1; ++x) {
+    for (int top = 0; top <= 1; ++top) {
+      int y = top ? o->ny - 1 : 0;
+      size_t n = node(o, x, y);
+      if (o->solid[n]) continue;
+      double* g = o->g + n * 9;
+      const double* fs = o->fs + n * 9;
+      double U = top ? o->u_top : o->u_bot;
+      switch (o->p.wall) {
+        case ORACLE_WALL_FREE_SLIP: /* Eq. 7: specular reflection */
+          if (top) {
+            g[S] = g[N];
+            g[SW] = g[NW];
+            g[SE] = g[NE];
+          } else {
+            g[N] = g[S];
+            g[NW] = g[SW];
+            g[NE] = g[SE];
+          }
+          break;
+        case ORACLE_WALL_NEBB: { /* Eqs. 9-10, density from the known populations */
+          if (top) {
+            double rw = g[R] + g[E] + g[Wd] + 2.0 * (g[N] + g[NE] + g[NW]);
+            g[S] = g[N];
+            g[SW] = g[NE] + 0.5 * (g[E] - g[Wd]) - 0.5 * rw * U;
+            g[SE] = g[NW] - 0.5 * (g[E] - g[Wd]) + 0.5 * rw * U;
+          } else {
+            double rw = g[R] + g[E] + g[Wd] + 2.0 * (g[S] + g[SW] + g[SE]);
+            g[N] = g[S];
+            g[NE] = g[SW] - 0.5 * (g[E] - g[Wd]) + 0.5 * rw * U;
+            g[NW] = g[SE] + 0.5 * (g[E] - g[Wd]) - 0.5 * rw * U;
+          }
+          break;
+        }
+        case ORACLE_WALL_MOVING_BB: { /* Eq. 11: f_opp(i) = f*_i - 2 w_i rho (c_i.u_w)/cs^2 */
+          double rho = o->rho_t[n];
+          const int out_top[3] = {N, NE, NW};
+          const int out_bot[3] = {S, SW, SE};
+          const int* outk = top ? out_top : out_bot;
+          for (int j = 0; j < 3; ++j) {
+            int k = outk[j];
+            g[OPP[k]] = fs[k] - 2.0 * W[k] * rho * (CX[k] * U) * 3.0;
+          }
+          break;
+        }
+        default:
+          break;
+      }
+    }
+  }
+}
+
+/* O5: zeroth-order extrapolation of the outlet column (Eq. 13). */
+static void outlet(oracle* o) {
+  if (o->p.x_periodic) return;
+  int xo = o->nx - 1, xi = o->nx - 2;
+  int corners = o->p.wall != ORACLE_WALL_PERIODIC;
+  for (int y = 0; y < o->ny; ++y) {
+    double* go = o->g + node(o, xo, y) * 9;
+    const double* gi = o->g + node(o, xi, y) * 9;
+    int all = o->p.outlet_mode == ORACLE_OUTLET_COPY_ALL || (corners && (y == 0 || y == o->ny - 1));
+    if (all) {
+      for (int k = 0; k < 9; ++k) go[k] = gi[k];
+    } else {
+      go[Wd] = gi[Wd];
+      go[NW] = gi[NW];
+      go[SW] = gi[SW];
+    }
+  }
+}
+
+/* O6: Zou-He velocity inlet with u = (U, 0).  The unknowns E, NE, SE follow
+ * from the three moment equations of Eq. 4 plus bounce-back of the
+ * non-equilibrium part normal to the inlet. */
+static void inlet(oracle* o) {
+  if (o->p.x_periodic) return;
+  double U = o->p.u_in;
+  int periodic = o->p.wall == ORACLE_WALL_PERIODIC;
+  int y0 = periodic ? 0 : 1, y1 = periodic ? o->ny - 1 : o->ny - 2;
+  for (int y = y0; y <= y1; ++y) {
+    double* g = o->g + node(o, 0, y) * 9;
+    double rho = (g[R] + g[N] + g[S] + 2.0 * (g[Wd] + g[NW] + g[SW])) / (1.0 - U);
+    g[E] = g[Wd] + (2.0 / 3.0) * rho * U;
+    g[NE] = g[SW] - 0.5 * (g[N] - g[S]) + rho * U / 6.0;
+    g[SE] = g[NW] + 0.5 * (g[N] - g[S]) + rho * U / 6.0;
+  }
+  if (!periodic) { /* O7: inlet corners are Dirichlet equilibrium nodes */
+    int ys[2] = {0, o->ny - 1};
+    for (int j = 0; j < 2; ++j) {
+      double* g = o->g + node(o, 0, ys[j]) * 9;
+      for (int k = 0; k < 9; ++k) g[k] = feq(k, 1.0, U, 0.0);
+    }
+  }
+}
+
+long oracle_step(oracle* o, long nsteps, double* fx, double* fy) {
+  for (long s = 0; s < nsteps; ++s) {
+    int bad = collide(o);
+    double Fx, Fy;
+    force(o, &Fx, &Fy);
+    if (fx) fx[s] = Fx;
+    if (fy) fy[s] = Fy;
+    stream(o);
+    walls(o);
+    outlet(o);
+    inlet(o);
+    /* O8 */
+    size_t nn = (size_t)o->nx * o->ny;
+    for (size_t n = 0; n < nn; ++n) {
+      if (o->solid[n]) continue;
+      for (int k = 0; k < 9; ++k) {
+        double v = o->g[n * 9 + k];
+        if (!isfinite(v)) bad = 1;
+        o->f[n * 9 + k] = v;
+      }
+    }
+    o->t += 1;
+    if (bad) return s + 1;
+  }
+  return 0;
+}
+
+void oracle_fields(const oracle* o, double* rho, double* ux, double* uy) {
+  size_t nn = (size_t)o->nx * o->ny;
+  for (size_t n = 0; n < nn; ++n) {
+    if (o->solid[n]) {
+      rho[n] = 1.0;
+      ux[n] = 0.0;
+      uy[n] = 0.0;
+      continue;
+    }
+    moments(o, o->f + n * 9, rho + n, ux + n, uy + n);
+  }
+}
+
+void oracle_get_f(const oracle* o, double* out) {
+  size_t nn = (size_t)o->nx * o->ny;
+  for (size_t n = 0; n < nn; ++n)
+    for (int k = 0; k < 9; ++k) out[k * nn + n] = o->f[n * 9 + k];
+}
+
+void oracle_set_f(oracle* o, const double* in) {
+  size_t nn = (size_t)o->nx * o->ny;
+  for (size_t n = 0; n < nn; ++n)
+    for (int k = 0; k < 9; ++k) o->f[n * 9 + k] = in[k * nn + n];
+  o->state_is_post = 0;
+}
+
+void oracle_get_fstar(const oracle* o, double* out) {
+  /* run the collision on a copy so the state is not advanced */
+  oracle tmp = *o;
+  size_t nn = (size_t)o->nx * o->ny;
+  tmp.fs = (double*)malloc(nn * 9 * sizeof(double));
+  tmp.rho_t = (double*)malloc(nn * sizeof(double));
+  if (!tmp.fs || !tmp.rho_t) {
+    free(tmp.fs);
+    free(tmp.rho_t);
+    for (size_t i = 0; i < nn * 9; ++i) out[i] = NAN;
+    return;
+  }
+  collide(&tmp);
+  for (size_t n = 0; n < nn; ++n)
+    for (int k = 0; k < 9; ++k) out[k * nn + n] = tmp.fs[n * 9 + k];
+  free(tmp.fs);
+  free(tmp.rho_t);
+}
+
+void oracle_set_fstar(oracle* o, const double* in) {
+  oracle_set_f(o, in);
+  o->state_is_post = 1;
+}
