@@ -1,0 +1,172 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) D2Q9 BGK solver for unconfined flow
+ * past a circular cylinder, after Sahiti, Gurugubelli & Surasani, "Lattice
+ * Boltzmann methodology for unconfined flows" (arXiv 2605.02185).
+ *
+ * Conventions (all entry points):
+ *  - Lattice units throughout: dx = dt = 1, c = 1, c_s^2 = 1/3 (Sec. 2.1).
+ *  - Directions k = 0..8 are the paper's Table 1 index minus one:
+ *      k : 0  1  2  3  4  5  6  7  8     (rest, E, N, W, S, NE, NW, SW, SE)
+ *      cx: 0  1  0 -1  0  1 -1 -1  1
+ *      cy: 0  0  1  0 -1  1  1 -1 -1
+ *  - Node (x, y) with x in [0, nx) along the flow, y in [0, ny) across it.
+ *    Column x = 0 is the velocity inlet, x = nx-1 the outlet, rows y = 0 and
+ *    y = ny-1 the bottom and top walls (wet-node placement, Sec. 2.4).
+ *  - Field arrays are row-major [ny][nx]; population arrays are [9][ny][nx].
+ *  - The library owns every device allocation it makes and frees it in the
+ *    matching destroy call.  Pointers passed in are owned by the caller and
+ *    are not retained after the call returns.
+ *  - Device pointers are HIP device addresses on the device that was current
+ *    when the context was created.  `stream` arguments are hipStream_t
+ *    values passed as void*; NULL is the null stream.
+ *  - Every function returns LBM_OK (0) or a negative lbm_status; the message
+ *    of the last failure on the calling thread is lbm_last_error().  Nothing
+ *    throws or exits across the ABI.
+ *  - One context is used by one host thread at a time.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_ERR_INVALID_ARG = -1, /* a parameter or argument is out of its documented range */
+  LBM_ERR_HIP = -2,         /* a HIP runtime call failed (message names it) */
+  LBM_ERR_OOM = -3,         /* device allocation failed */
+  LBM_ERR_DIVERGED = -4,    /* a fluid density became non-finite or left (0, 10) */
+  LBM_ERR_RANGE = -5,       /* requested force steps are not (or no longer) stored */
+  LBM_ERR_STATE = -6        /* call not valid in the context's current state */
+} lbm_status;
+
+/* Top/bottom treatments of Sec. 2.3 (the four the paper compares). */
+typedef enum {
+  LBM_WALL_FREE_SLIP = 0, /* Eq. 7: specular reflection of the missing populations */
+  LBM_WALL_PERIODIC = 1,  /* Eq. 8, realised as wrap-around streaming in y */
+  LBM_WALL_NEBB = 2,      /* Eqs. 9-10: Zou-He wet-node wall moving at (U_w, 0) */
+  LBM_WALL_MOVING_BB = 3  /* Eq. 11: bounce-back of a wall moving at (U_w, 0) */
+} lbm_wall;
+
+/* Outlet of Eq. 13 (zeroth-order extrapolation from column nx-2). */
+typedef enum {
+  LBM_OUTLET_COPY_ALL = 0,    /* all nine populations (Eq. 13 as printed) */
+  LBM_OUTLET_COPY_UNKNOWN = 1 /* only W, NW, SW; all nine at the two outlet corners */
+} lbm_outlet;
+
+typedef struct {
+  int32_t struct_size;   /* sizeof(lbm_params); set by lbm_params_init */
+  int32_t nx, ny;        /* lattice size, both >= 3 */
+  int32_t diameter;      /* cylinder diameter D in lattice units; 0 = no cylinder */
+  int32_t cx2, cy2;      /* cylinder centre in doubled coordinates (2 x_c, 2 y_c) */
+  double u_in;           /* inlet velocity U, 0 <= U < 1/sqrt(3) */
+  double re;             /* Reynolds number, used when tau <= 0 */
+  double tau;            /* BGK relaxation time; <= 0 derives it by Eqs. 16-17 */
+  int32_t wall;          /* lbm_wall for both the top and the bottom row */
+  int32_t outlet_mode;   /* lbm_outlet */
+  double u_wall_top;     /* wall tangential velocity (NEBB, moving BB); NaN = u_in */
+  double u_wall_bottom;  /* same for the bottom row; NaN = u_in */
+  int32_t x_periodic;    /* 1: periodic in x, no inlet/outlet (test boxes) */
+  int32_t reserved0;
+  double perturb_amp;    /* initial v = amp * U * sin(2 pi y/(ny-1)) */
+  int64_t hist_capacity; /* force steps kept on the device (ring buffer) */
+} lbm_params;
+
+/* Defaults: D = 0, centre 21*D doubled (10.5 D), U = 0.1, Re = 100, tau
+ * derived, free-slip walls, copy-all outlet, perturbation 1e-3, history of
+ * 1<<20 steps.  nx and ny are set to 0 and must be filled in. */
+void lbm_params_init(lbm_params* p);
+
+/* Host-only check of a parameter set (no GPU needed).  Rejects nx or ny < 3,
+ * tau <= 1/2, U outside [0, 1/sqrt(3)), an unknown wall or outlet mode, a
+ * cylinder with a solid node outside [3, nx-4] x [3, ny-4] (so that two fluid
+ * nodes separate it from every edge row and column), and hist_capacity < 1. */
+lbm_status lbm_validate_params(const lbm_params* p);
+
+/* tau actually used: p->tau if > 0, else 3 U D / Re + 1/2 (Eqs. 16-17). */
+double lbm_params_tau(const lbm_params* p);
+
+/* Host-only geometry of the staircase disk (Sec. 2.5, Fig. 4): node (x, y)
+ * is solid iff (2x - cx2)^2 + (2y - cy2)^2 <= D^2.  Outputs may be NULL:
+ * solid_mask [ny][nx] 0/1, the number of solid nodes, of fluid nodes with a
+ * solid neighbour, and of fluid-to-solid links over all 8 directions. */
+lbm_status lbm_geometry(const lbm_params* p, uint8_t* solid_mask, int64_t* n_solid,
+                        int64_t* n_boundary_nodes, int64_t* n_links);
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Validate p, allocate the device state on the current device and initialise
+ * it to the equilibrium of rho = 1, u = (U, amp U sin(2 pi y/(ny-1))) (Eq. 3).
+ * All later work of the context is ordered on `stream`. */
+lbm_status lbm_create(const lbm_params* p, void* stream, lbm_ctx** out);
+
+/* Release every device allocation of the context (synchronises its stream). */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Advance n >= 0 time steps.  One step is, per node, the pull of the
+ * post-collision populations of the neighbours (streaming, Eq. 2), half-way
+ * bounce-back at the cylinder (Sec. 3.1), the boundary corrections of
+ * Sec. 2.3 and the inlet, then the BGK collision (Eqs. 2-4); the force on the
+ * cylinder is taken by momentum exchange (Eq. 14) in the same pass.
+ * Stream-ordered and asynchronous; a divergence is reported by the next
+ * lbm_sync / lbm_forces / lbm_fields / lbm_get_populations call. */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Wait for the context's stream; LBM_ERR_DIVERGED if a step went bad. */
+lbm_status lbm_sync(lbm_ctx* ctx);
+
+/* Steps completed so far. */
+lbm_status lbm_get_step(lbm_ctx* ctx, int64_t* step);
+
+/* First step that diverged (1-based), or 0 if none (synchronises). */
+lbm_status lbm_diverged_step(lbm_ctx* ctx, int64_t* step);
+
+/* Force on the cylinder by momentum exchange (Eq. 14), accumulated in FP64,
+ * and its coefficients (Eq. 15 with rho_in = 1 and the nominal D).  Step k
+ * (1-based) is the force exchanged while streaming from time k-1 to k.
+ * Copies steps [first, first+count) into the host arrays fx, fy, cd, cl (any
+ * may be NULL).  LBM_ERR_RANGE if a step was not yet run or has left the
+ * ring of hist_capacity steps.  cd/cl need D > 0 and U > 0. */
+lbm_status lbm_forces(lbm_ctx* ctx, int64_t first, int64_t count, double* fx, double* fy,
+                      double* cd, double* cl);
+
+/* Density and velocity (Eq. 4) of the current state into caller arrays
+ * [ny][nx] (host memory if on_device == 0, device memory otherwise).  Solid
+ * nodes report rho = 1, u = 0.  Any pointer may be NULL. */
+lbm_status lbm_fields(lbm_ctx* ctx, float* rho, float* ux, float* uy, int on_device);
+
+/* State exchange, layout [9][ny][nx].  The state between steps is the set of
+ * post-collision populations f*(x, t) (what streams next).  dtype 0 = float32,
+ * 1 = float64 (converted on the device).  Setting the state keeps the step
+ * counter and force history; the next step streams the given populations. */
+lbm_status lbm_get_populations(lbm_ctx* ctx, void* buf, int dtype, int on_device);
+lbm_status lbm_set_populations(lbm_ctx* ctx, const void* buf, int dtype, int on_device);
+
+/* Shedding statistics of a coefficient history (host-only): periods from the
+ * upward crossings of cl through its mean (linear interpolation between
+ * steps), St = D/(T U) with T the mean period over the last `periods`
+ * periods, cl amplitude = (max-min)/2 and mean cd over those periods.
+ * LBM_ERR_RANGE if fewer than periods+1 crossings exist. */
+typedef struct {
+  double mean_cd, cl_amp, st, period;
+} lbm_shedding;
+lbm_status lbm_shedding_stats(const double* cd, const double* cl, int64_t n, double d, double u,
+                              int32_t periods, lbm_shedding* out);
+
+/* Kernel selection for measurement and autotuning: variant 0 = automatic.
+ * Valid variants are 1..lbm_num_variants(); the result is bit-identical for
+ * every variant. */
+int32_t lbm_num_variants(void);
+lbm_status lbm_set_variant(lbm_ctx* ctx, int32_t variant);
+const char* lbm_variant_name(int32_t variant);
+
+/* Thread-local message of the last failure ("" if none). */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

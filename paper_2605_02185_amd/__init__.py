@@ -1,0 +1,172 @@
+"""MI355X-native D2Q9 BGK lattice Boltzmann solver for unconfined flow past a
+circular cylinder (arXiv 2605.02185), behind the C ABI of include/lbm.h.
+
+``Lattice`` wraps one solver context.  PyTorch is used only to hand device
+buffers and the current HIP stream to the library; all arithmetic runs in the
+library's gfx950 kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (
+    OUTLET_COPY_ALL,
+    OUTLET_COPY_UNKNOWN,
+    WALL_FREE_SLIP,
+    WALL_MOVING_BB,
+    WALL_NEBB,
+    WALL_PERIODIC,
+    DivergedError,
+    LbmError,
+    RangeError,
+    check,
+    make_params,
+)
+
+__all__ = [
+    "Lattice", "make_params", "validate", "tau_of", "geometry", "shedding_stats",
+    "num_variants", "variant_name", "LbmError", "DivergedError", "RangeError",
+    "WALL_FREE_SLIP", "WALL_PERIODIC", "WALL_NEBB", "WALL_MOVING_BB",
+    "OUTLET_COPY_ALL", "OUTLET_COPY_UNKNOWN",
+]
+
+
+def validate(p: _lib.Params):
+    check(_lib.lib.lbm_validate_params(ctypes.byref(p)))
+
+
+def tau_of(p: _lib.Params) -> float:
+    return _lib.lib.lbm_params_tau(ctypes.byref(p))
+
+
+def geometry(p: _lib.Params):
+    """(solid mask [ny][nx] uint8, n_solid, n_boundary_nodes, n_links); host only."""
+    mask = np.zeros((p.ny, p.nx), dtype=np.uint8)
+    ns, nb, nl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    check(_lib.lib.lbm_geometry(ctypes.byref(p), mask.ctypes.data, ctypes.byref(ns), ctypes.byref(nb),
+                                ctypes.byref(nl)))
+    return mask, ns.value, nb.value, nl.value
+
+
+def shedding_stats(cd, cl, d, u, periods=5):
+    cd = np.ascontiguousarray(cd, dtype=np.float64)
+    cl = np.ascontiguousarray(cl, dtype=np.float64)
+    out = _lib.Shedding()
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(_lib.lib.lbm_shedding_stats(cd.ctypes.data_as(dp), cl.ctypes.data_as(dp), len(cd), d, u,
+                                      periods, ctypes.byref(out)))
+    return {"mean_cd": out.mean_cd, "cl_amp": out.cl_amp, "st": out.st, "period": out.period}
+
+
+def num_variants() -> int:
+    return _lib.lib.lbm_num_variants()
+
+
+def variant_name(v: int) -> str:
+    return _lib.lib.lbm_variant_name(v).decode()
+
+
+def _stream_handle(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Lattice:
+    """One solver context on the current device, ordered on `stream`
+    (default: torch's current stream)."""
+
+    def __init__(self, params: _lib.Params, stream=None):
+        self.params = params
+        self.nx, self.ny = params.nx, params.ny
+        self._h = ctypes.c_void_p()
+        check(_lib.lib.lbm_create(ctypes.byref(params), _stream_handle(stream), ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            _lib.lib.lbm_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------ steps
+    def step(self, n: int = 1):
+        check(_lib.lib.lbm_step(self._h, n))
+
+    def sync(self):
+        check(_lib.lib.lbm_sync(self._h))
+
+    @property
+    def t(self) -> int:
+        s = ctypes.c_int64()
+        check(_lib.lib.lbm_get_step(self._h, ctypes.byref(s)))
+        return s.value
+
+    def diverged_step(self) -> int:
+        s = ctypes.c_int64()
+        check(_lib.lib.lbm_diverged_step(self._h, ctypes.byref(s)))
+        return s.value
+
+    def set_variant(self, v: int):
+        check(_lib.lib.lbm_set_variant(self._h, v))
+
+    # ---------------------------------------------------------------- outputs
+    def forces(self, first: int = 1, count: int | None = None):
+        """(fx, fy, cd, cl) for steps [first, first+count); cd/cl None without a cylinder."""
+        if count is None:
+            count = self.t - first + 1
+        fx, fy = np.zeros(count), np.zeros(count)
+        coeff = self.params.diameter > 0 and self.params.u_in > 0
+        cd = np.zeros(count) if coeff else None
+        cl = np.zeros(count) if coeff else None
+        check(_lib.lib.lbm_forces(self._h, first, count, fx.ctypes.data, fy.ctypes.data,
+                                  cd.ctypes.data if coeff else None, cl.ctypes.data if coeff else None))
+        return fx, fy, cd, cl
+
+    def fields(self):
+        """Host float32 arrays rho, ux, uy [ny][nx]."""
+        shape = (self.ny, self.nx)
+        rho, ux, uy = (np.empty(shape, np.float32) for _ in range(3))
+        check(_lib.lib.lbm_fields(self._h, rho.ctypes.data, ux.ctypes.data, uy.ctypes.data, 0))
+        return rho, ux, uy
+
+    def fields_device(self, rho, ux, uy):
+        """Fill caller-owned device tensors (float32, [ny][nx], contiguous)."""
+        ptr = [t.data_ptr() if t is not None else None for t in (rho, ux, uy)]
+        check(_lib.lib.lbm_fields(self._h, *ptr, 1))
+
+    def get_populations(self, dtype=np.float32):
+        dt = 0 if np.dtype(dtype) == np.float32 else 1
+        out = np.empty((9, self.ny, self.nx), dtype=np.float32 if dt == 0 else np.float64)
+        check(_lib.lib.lbm_get_populations(self._h, out.ctypes.data, dt, 0))
+        return out
+
+    def set_populations(self, f):
+        f = np.asarray(f)
+        dt = 0 if f.dtype == np.float32 else 1
+        a = np.ascontiguousarray(f, dtype=np.float32 if dt == 0 else np.float64)
+        assert a.shape == (9, self.ny, self.nx)
+        check(_lib.lib.lbm_set_populations(self._h, a.ctypes.data, dt, 0))
+
+    def get_populations_device(self, t):
+        dt = 0 if str(t.dtype) == "torch.float32" else 1
+        check(_lib.lib.lbm_get_populations(self._h, t.data_ptr(), dt, 1))
+
+    def set_populations_device(self, t):
+        dt = 0 if str(t.dtype) == "torch.float32" else 1
+        check(_lib.lib.lbm_set_populations(self._h, t.data_ptr(), dt, 1))

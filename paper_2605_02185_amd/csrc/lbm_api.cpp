@@ -1,0 +1,534 @@
+// Host runtime of liblbm.so: parameter validation, geometry, device state,
+// step scheduling and the C ABI of include/lbm.h.
+#include "../../include/lbm.h"
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+lbm_status fail(lbm_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(e_ == hipErrorOutOfMemory ? LBM_ERR_OOM : LBM_ERR_HIP, "%s: %s (%s:%d)", \
+                  #call, hipGetErrorString(e_), __FILE__, __LINE__);                      \
+  } while (0)
+
+// Table 1 with k = i - 1 (host copy for geometry and link flags).
+const int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+bool solid_at(const lbm_params& p, int x, int y) {
+  if (p.diameter <= 0) return false;
+  const int64_t dx = 2LL * x - p.cx2, dy = 2LL * y - p.cy2;
+  return dx * dx + dy * dy <= (int64_t)p.diameter * p.diameter;
+}
+
+double wall_u(double v, double u_in) { return std::isnan(v) ? u_in : v; }
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p{};
+  double tau = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  lbm::Geometry geo{};
+  lbm::Physics phys{};
+  lbm::Tiling tiling{};
+  int variant = 1;
+  float* buf[2] = {nullptr, nullptr};
+  int cur = 0;
+  uint16_t* d_flags = nullptr;
+  double2* d_partials = nullptr;
+  int max_slots = 0;
+  double* d_hist = nullptr;
+  int64_t* d_step = nullptr;
+  int* d_bad = nullptr;
+  int64_t* d_bad_step = nullptr;
+  int64_t step = 0;
+  int pending = 0;
+};
+
+extern "C" {
+
+void lbm_params_init(lbm_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->struct_size = (int32_t)sizeof(lbm_params);
+  p->u_in = 0.1;
+  p->re = 100.0;
+  p->tau = 0.0;
+  p->wall = LBM_WALL_FREE_SLIP;
+  p->outlet_mode = LBM_OUTLET_COPY_ALL;
+  p->u_wall_top = NAN;
+  p->u_wall_bottom = NAN;
+  p->perturb_amp = 1e-3;
+  p->hist_capacity = 1 << 20;
+}
+
+double lbm_params_tau(const lbm_params* p) {
+  if (!p) return NAN;
+  if (p->tau > 0) return p->tau;
+  const double nu = p->u_in * p->diameter / p->re;  // Eq. 16
+  return 3.0 * nu + 0.5;                            // Eq. 17
+}
+
+lbm_status lbm_validate_params(const lbm_params* p) {
+  if (!p) return fail(LBM_ERR_INVALID_ARG, "params is NULL");
+  if (p->struct_size != (int32_t)sizeof(lbm_params))
+    return fail(LBM_ERR_INVALID_ARG, "struct_size %d != %d (call lbm_params_init)", p->struct_size,
+                (int)sizeof(lbm_params));
+  if (p->nx < 3 || p->ny < 3) return fail(LBM_ERR_INVALID_ARG, "nx, ny must be >= 3 (got %d, %d)", p->nx, p->ny);
+  if (p->wall < LBM_WALL_FREE_SLIP || p->wall > LBM_WALL_MOVING_BB)
+    return fail(LBM_ERR_INVALID_ARG, "unknown wall mode %d", p->wall);
+  if (p->outlet_mode != LBM_OUTLET_COPY_ALL && p->outlet_mode != LBM_OUTLET_COPY_UNKNOWN)
+    return fail(LBM_ERR_INVALID_ARG, "unknown outlet mode %d", p->outlet_mode);
+  if (p->x_periodic != 0 && p->x_periodic != 1) return fail(LBM_ERR_INVALID_ARG, "x_periodic must be 0 or 1");
+  if (!(p->u_in >= 0.0 && p->u_in < 1.0 / std::sqrt(3.0)))
+    return fail(LBM_ERR_INVALID_ARG, "u_in = %g outside [0, 1/sqrt(3))", p->u_in);
+  if (p->tau <= 0 && !(p->re > 0)) return fail(LBM_ERR_INVALID_ARG, "re must be > 0 when tau is derived");
+  const double tau = lbm_params_tau(p);
+  if (!(tau > 0.5) || !std::isfinite(tau)) return fail(LBM_ERR_INVALID_ARG, "tau = %g must be > 1/2", tau);
+  for (double uw : {p->u_wall_top, p->u_wall_bottom})
+    if (!std::isnan(uw) && !(std::fabs(uw) < 1.0 / std::sqrt(3.0)))
+      return fail(LBM_ERR_INVALID_ARG, "wall velocity %g out of range", uw);
+  if (p->diameter < 0) return fail(LBM_ERR_INVALID_ARG, "diameter must be >= 0");
+  if (p->diameter > 0) {
+    // bounding box of the disk in doubled coordinates: [c - D, c + D]
+    const int64_t xlo = p->cx2 - p->diameter, xhi = p->cx2 + p->diameter;
+    const int64_t ylo = p->cy2 - p->diameter, yhi = p->cy2 + p->diameter;
+    // 2-node margin: every node within 2 of a solid node lies inside [1, n-2]
+    if (xlo < 2 * 3 || xhi > 2 * ((int64_t)p->nx - 4) || ylo < 2 * 3 || yhi > 2 * ((int64_t)p->ny - 4))
+      return fail(LBM_ERR_INVALID_ARG, "cylinder must stay at least 2 nodes away from every edge");
+  }
+  if (p->hist_capacity < 1) return fail(LBM_ERR_INVALID_ARG, "hist_capacity must be >= 1");
+  if (!std::isfinite(p->perturb_amp)) return fail(LBM_ERR_INVALID_ARG, "perturb_amp must be finite");
+  return LBM_OK;
+}
+
+lbm_status lbm_geometry(const lbm_params* p, uint8_t* solid_mask, int64_t* n_solid,
+                        int64_t* n_boundary_nodes, int64_t* n_links) {
+  if (!p || p->nx < 1 || p->ny < 1) return fail(LBM_ERR_INVALID_ARG, "bad params");
+  int64_t ns = 0, nb = 0, nl = 0;
+  for (int y = 0; y < p->ny; ++y)
+    for (int x = 0; x < p->nx; ++x) {
+      const bool s = solid_at(*p, x, y);
+      if (solid_mask) solid_mask[(int64_t)y * p->nx + x] = s ? 1 : 0;
+      if (s) {
+        ++ns;
+        continue;
+      }
+      int links = 0;
+      for (int k = 1; k < 9; ++k) links += solid_at(*p, x + CX[k], y + CY[k]);
+      nl += links;
+      nb += links > 0;
+    }
+  if (n_solid) *n_solid = ns;
+  if (n_boundary_nodes) *n_boundary_nodes = nb;
+  if (n_links) *n_links = nl;
+  return LBM_OK;
+}
+
+int32_t lbm_num_variants(void) { return lbm::num_variants(); }
+
+const char* lbm_variant_name(int32_t v) {
+  if (v < 1 || v > lbm::num_variants()) return "";
+  return lbm::variant(v).name;
+}
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+namespace {
+
+void set_tiling(lbm_ctx* c, int v) {
+  const lbm::Variant& var = lbm::variant(v);
+  lbm::Tiling& t = c->tiling;
+  t.tile_x = var.tile_x;
+  t.tile_y = var.tile_y;
+  t.ntx = (c->geo.nx + t.tile_x - 1) / t.tile_x;
+  t.nty = (c->geo.ny + t.tile_y - 1) / t.tile_y;
+  t.remap_xcd = var.remap_xcd;
+  if (c->geo.rw > 0) {
+    t.fx0 = c->geo.rx0 / t.tile_x;
+    t.fy0 = c->geo.ry0 / t.tile_y;
+    t.fw = (c->geo.rx0 + c->geo.rw - 1) / t.tile_x - t.fx0 + 1;
+    t.fh = (c->geo.ry0 + c->geo.rh - 1) / t.tile_y - t.fy0 + 1;
+  } else {  // no cylinder: one tile reports the zero force
+    t.fx0 = t.fy0 = 0;
+    t.fw = t.fh = 1;
+  }
+  c->variant = v;
+}
+
+int slots_of(const lbm_ctx* c) { return c->tiling.fw * c->tiling.fh; }
+
+lbm_status flush(lbm_ctx* c) {
+  if (c->pending == 0) return LBM_OK;
+  HIP_TRY(lbm::launch_force_reduce(c->d_partials, slots_of(c), c->pending, c->d_hist,
+                                   c->p.hist_capacity, c->d_step, c->d_bad, c->d_bad_step, c->stream));
+  c->pending = 0;
+  return LBM_OK;
+}
+
+void free_ctx(lbm_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(c->buf[0]);
+  (void)hipFree(c->buf[1]);
+  (void)hipFree(c->d_flags);
+  (void)hipFree(c->d_partials);
+  (void)hipFree(c->d_hist);
+  (void)hipFree(c->d_step);
+  (void)hipFree(c->d_bad);
+  (void)hipFree(c->d_bad_step);
+  delete c;
+}
+
+lbm_status check_ctx(lbm_ctx* c) {
+  if (!c) return fail(LBM_ERR_INVALID_ARG, "context is NULL");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_create(const lbm_params* p, void* stream, lbm_ctx** out) {
+  if (!out) return fail(LBM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  lbm_status st = lbm_validate_params(p);
+  if (st != LBM_OK) return st;
+  lbm_ctx* c = new lbm_ctx();
+  c->p = *p;
+  c->tau = lbm_params_tau(p);
+  c->stream = (hipStream_t)stream;
+  {
+    const hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(LBM_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+  }
+  lbm::Geometry& g = c->geo;
+  g.nx = p->nx;
+  g.ny = p->ny;
+  g.pitch = (p->nx + 63) / 64 * 64;
+  g.plane = ((int64_t)p->ny * g.pitch + 63) / 64 * 64;
+  if (9 * g.plane >= (int64_t)INT_MAX) {
+    delete c;
+    return fail(LBM_ERR_INVALID_ARG, "lattice of %d x %d exceeds the 32-bit offsets of the kernels", p->nx, p->ny);
+  }
+  // cylinder rectangle: solid nodes plus one ring of fluid neighbours
+  std::vector<uint16_t> flags;
+  if (p->diameter > 0) {
+    int x0 = INT_MAX, x1 = -1, y0 = INT_MAX, y1 = -1;
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x)
+        if (solid_at(*p, x, y)) {
+          x0 = std::min(x0, x);
+          x1 = std::max(x1, x);
+          y0 = std::min(y0, y);
+          y1 = std::max(y1, y);
+        }
+    if (x1 >= 0) {
+      g.rx0 = x0 - 1;
+      g.ry0 = y0 - 1;
+      g.rw = x1 - x0 + 3;
+      g.rh = y1 - y0 + 3;
+      flags.resize((size_t)g.rw * g.rh);
+      for (int j = 0; j < g.rh; ++j)
+        for (int i = 0; i < g.rw; ++i) {
+          const int x = g.rx0 + i, y = g.ry0 + j;
+          uint16_t f = 0;
+          if (solid_at(*p, x, y)) {
+            f = lbm::kSolid;
+          } else {
+            for (int k = 1; k < 9; ++k)
+              if (solid_at(*p, x - CX[k], y - CY[k])) f |= (uint16_t)(1u << k);
+          }
+          flags[(size_t)j * g.rw + i] = f;
+        }
+    }
+  }
+  lbm::Physics& ph = c->phys;
+  ph.omega = (float)(1.0 / c->tau);
+  ph.u_in = (float)p->u_in;
+  ph.u_top = (float)wall_u(p->u_wall_top, p->u_in);
+  ph.u_bot = (float)wall_u(p->u_wall_bottom, p->u_in);
+  ph.wall = p->wall;
+  ph.outlet_mode = p->outlet_mode;
+  ph.x_periodic = p->x_periodic;
+
+  // the largest number of force slots over all variants sizes the ring
+  for (int v = 1; v <= lbm::num_variants(); ++v) {
+    set_tiling(c, v);
+    c->max_slots = std::max(c->max_slots, slots_of(c));
+  }
+  set_tiling(c, 1);
+
+#define CREATE_TRY(call)            \
+  do {                              \
+    lbm_status s_ = [&]() -> lbm_status { HIP_TRY(call); return LBM_OK; }(); \
+    if (s_ != LBM_OK) {             \
+      free_ctx(c);                  \
+      return s_;                    \
+    }                               \
+  } while (0)
+
+  const size_t fbytes = (size_t)9 * g.plane * sizeof(float);
+  CREATE_TRY(hipMalloc(&c->buf[0], fbytes));
+  CREATE_TRY(hipMalloc(&c->buf[1], fbytes));
+  CREATE_TRY(hipMemsetAsync(c->buf[0], 0, fbytes, c->stream));
+  CREATE_TRY(hipMemsetAsync(c->buf[1], 0, fbytes, c->stream));
+  if (!flags.empty()) {
+    CREATE_TRY(hipMalloc(&c->d_flags, flags.size() * sizeof(uint16_t)));
+    CREATE_TRY(hipMemcpyAsync(c->d_flags, flags.data(), flags.size() * sizeof(uint16_t),
+                              hipMemcpyHostToDevice, c->stream));
+  }
+  g.flags = c->d_flags;
+  CREATE_TRY(hipMalloc(&c->d_partials, sizeof(double2) * (size_t)c->max_slots * lbm::kRing));
+  CREATE_TRY(hipMalloc(&c->d_hist, sizeof(double) * 2 * (size_t)p->hist_capacity));
+  CREATE_TRY(hipMemsetAsync(c->d_hist, 0, sizeof(double) * 2 * (size_t)p->hist_capacity, c->stream));
+  CREATE_TRY(hipMalloc(&c->d_step, sizeof(int64_t)));
+  CREATE_TRY(hipMalloc(&c->d_bad_step, sizeof(int64_t)));
+  CREATE_TRY(hipMalloc(&c->d_bad, sizeof(int)));
+  CREATE_TRY(hipMemsetAsync(c->d_step, 0, sizeof(int64_t), c->stream));
+  CREATE_TRY(hipMemsetAsync(c->d_bad_step, 0, sizeof(int64_t), c->stream));
+  CREATE_TRY(lbm::launch_fill_int(c->d_bad, INT_MAX, c->stream));
+  CREATE_TRY(lbm::launch_init_equilibrium(c->buf[0], g, p->u_in, p->perturb_amp, c->stream));
+  CREATE_TRY(hipStreamSynchronize(c->stream));
+#undef CREATE_TRY
+  *out = c;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* ctx) { free_ctx(ctx); }
+
+lbm_status lbm_set_variant(lbm_ctx* c, int32_t v) {
+  if (check_ctx(c)) return LBM_ERR_INVALID_ARG;
+  if (v == 0) v = 1;
+  if (v < 1 || v > lbm::num_variants()) return fail(LBM_ERR_INVALID_ARG, "variant %d out of range", v);
+  lbm_status st = flush(c);
+  if (st != LBM_OK) return st;
+  set_tiling(c, v);
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+  if (check_ctx(c)) return LBM_ERR_INVALID_ARG;
+  if (n < 0) return fail(LBM_ERR_INVALID_ARG, "n must be >= 0");
+  const int nslots = slots_of(c);
+  lbm::StepArgs a{};
+  a.g = c->geo;
+  a.p = c->phys;
+  a.t = c->tiling;
+  a.bad = c->d_bad;
+  for (int64_t i = 0; i < n; ++i) {
+    a.A = c->buf[c->cur];
+    a.B = c->buf[c->cur ^ 1];
+    a.slot = c->pending;
+    a.partial = c->d_partials + (size_t)c->pending * nslots;
+    HIP_TRY(lbm::launch_step(a, c->variant, c->stream));
+    c->cur ^= 1;
+    c->step += 1;
+    if (++c->pending == lbm::kRing) {
+      lbm_status st = flush(c);
+      if (st != LBM_OK) return st;
+    }
+  }
+  return flush(c);
+}
+
+lbm_status lbm_sync(lbm_ctx* c) {
+  if (check_ctx(c)) return LBM_ERR_INVALID_ARG;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  int64_t bad = 0;
+  HIP_TRY(hipMemcpy(&bad, c->d_bad_step, sizeof bad, hipMemcpyDeviceToHost));
+  if (bad) return fail(LBM_ERR_DIVERGED, "density left (0, 10) or became non-finite at step %lld", (long long)bad);
+  return LBM_OK;
+}
+
+lbm_status lbm_get_step(lbm_ctx* c, int64_t* step) {
+  if (check_ctx(c) || !step) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+  *step = c->step;
+  return LBM_OK;
+}
+
+lbm_status lbm_diverged_step(lbm_ctx* c, int64_t* step) {
+  if (check_ctx(c) || !step) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(step, c->d_bad_step, sizeof *step, hipMemcpyDeviceToHost));
+  return LBM_OK;
+}
+
+lbm_status lbm_forces(lbm_ctx* c, int64_t first, int64_t count, double* fx, double* fy, double* cd,
+                      double* cl) {
+  if (check_ctx(c)) return LBM_ERR_INVALID_ARG;
+  if (count < 0 || first < 1) return fail(LBM_ERR_INVALID_ARG, "first must be >= 1 and count >= 0");
+  const int64_t cap = c->p.hist_capacity;
+  if (first + count - 1 > c->step || first <= c->step - cap)
+    return fail(LBM_ERR_RANGE, "steps [%lld, %lld] not stored (have (%lld, %lld])", (long long)first,
+                (long long)(first + count - 1), (long long)std::max<int64_t>(0, c->step - cap),
+                (long long)c->step);
+  if ((cd || cl) && !(c->p.u_in > 0 && c->p.diameter > 0))
+    return fail(LBM_ERR_INVALID_ARG, "coefficients need u_in > 0 and diameter > 0");
+  lbm_status st = lbm_sync(c);
+  if (st != LBM_OK && st != LBM_ERR_DIVERGED) return st;
+  if (count == 0) return st;
+  std::vector<double> h((size_t)2 * count);
+  // the ring may wrap: copy in at most two pieces
+  int64_t done = 0;
+  while (done < count) {
+    const int64_t s = (first - 1 + done) % cap;
+    const int64_t n = std::min(count - done, cap - s);
+    HIP_TRY(hipMemcpy(h.data() + 2 * done, c->d_hist + 2 * s, sizeof(double) * 2 * n, hipMemcpyDeviceToHost));
+    done += n;
+  }
+  const double q = 0.5 * 1.0 * c->p.u_in * c->p.u_in * c->p.diameter;  // Eq. 15, rho_in = 1
+  for (int64_t i = 0; i < count; ++i) {
+    if (fx) fx[i] = h[2 * i];
+    if (fy) fy[i] = h[2 * i + 1];
+    if (cd) cd[i] = h[2 * i] / q;
+    if (cl) cl[i] = h[2 * i + 1] / q;
+  }
+  return st;
+}
+
+lbm_status lbm_fields(lbm_ctx* c, float* rho, float* ux, float* uy, int on_device) {
+  if (check_ctx(c)) return LBM_ERR_INVALID_ARG;
+  const lbm::Geometry& g = c->geo;
+  const size_t n = (size_t)g.nx * g.ny;
+  if (on_device) {
+    HIP_TRY(lbm::launch_fields(c->buf[c->cur], g, rho, ux, uy, c->stream));
+    return lbm_sync(c);
+  }
+  float* d = nullptr;
+  HIP_TRY(hipMalloc(&d, 3 * n * sizeof(float)));
+  lbm_status st = LBM_OK;
+  hipError_t e = lbm::launch_fields(c->buf[c->cur], g, d, d + n, d + 2 * n, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess && rho) e = hipMemcpy(rho, d, n * sizeof(float), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && ux) e = hipMemcpy(ux, d + n, n * sizeof(float), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && uy) e = hipMemcpy(uy, d + 2 * n, n * sizeof(float), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) st = fail(LBM_ERR_HIP, "lbm_fields: %s", hipGetErrorString(e));
+  (void)hipFree(d);
+  if (st != LBM_OK) return st;
+  return lbm_sync(c);
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, void* buf, int dtype, int on_device) {
+  if (check_ctx(c) || !buf) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+  if (dtype != 0 && dtype != 1) return fail(LBM_ERR_INVALID_ARG, "dtype must be 0 (f32) or 1 (f64)");
+  const lbm::Geometry& g = c->geo;
+  const size_t bytes = (size_t)9 * g.nx * g.ny * (dtype ? 8 : 4);
+  if (on_device) {
+    HIP_TRY(lbm::launch_pack(c->buf[c->cur], g, buf, dtype, c->stream));
+    return lbm_sync(c);
+  }
+  void* d = nullptr;
+  HIP_TRY(hipMalloc(&d, bytes));
+  hipError_t e = lbm::launch_pack(c->buf[c->cur], g, d, dtype, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipMemcpy(buf, d, bytes, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(LBM_ERR_HIP, "lbm_get_populations: %s", hipGetErrorString(e));
+  return lbm_sync(c);
+}
+
+lbm_status lbm_set_populations(lbm_ctx* c, const void* buf, int dtype, int on_device) {
+  if (check_ctx(c) || !buf) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+  if (dtype != 0 && dtype != 1) return fail(LBM_ERR_INVALID_ARG, "dtype must be 0 (f32) or 1 (f64)");
+  const lbm::Geometry& g = c->geo;
+  const size_t bytes = (size_t)9 * g.nx * g.ny * (dtype ? 8 : 4);
+  if (on_device) {
+    HIP_TRY(lbm::launch_unpack(buf, dtype, g, c->buf[c->cur], c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+  }
+  void* d = nullptr;
+  HIP_TRY(hipMalloc(&d, bytes));
+  hipError_t e = hipMemcpyAsync(d, buf, bytes, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = lbm::launch_unpack(d, dtype, g, c->buf[c->cur], c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(LBM_ERR_HIP, "lbm_set_populations: %s", hipGetErrorString(e));
+  return LBM_OK;
+}
+
+// ------------------------------------------------------------------ statistics
+lbm_status lbm_shedding_stats(const double* cd, const double* cl, int64_t n, double d, double u,
+                              int32_t periods, lbm_shedding* out) {
+  if (!cd || !cl || !out || n < 2 || periods < 1 || !(u > 0) || !(d > 0))
+    return fail(LBM_ERR_INVALID_ARG, "bad arguments to lbm_shedding_stats");
+  auto crossings = [&](double level, std::vector<double>& xs) {
+    xs.clear();
+    for (int64_t i = 0; i + 1 < n; ++i) {
+      const double a = cl[i] - level, b = cl[i + 1] - level;
+      if (a < 0.0 && b >= 0.0) xs.push_back((double)i + (-a) / (b - a));
+    }
+  };
+  double mean = 0.0;
+  for (int64_t i = 0; i < n; ++i) mean += cl[i];
+  mean /= (double)n;
+  std::vector<double> xs;
+  crossings(mean, xs);
+  if ((int64_t)xs.size() < periods + 1) return fail(LBM_ERR_RANGE, "only %zu lift crossings", xs.size());
+  double a0 = xs[xs.size() - periods - 1], a1 = xs.back();
+  double T = (a1 - a0) / periods;
+  int64_t i0 = (int64_t)std::ceil(a0), i1 = (int64_t)std::floor(a1);
+  // second pass about the window's own mean
+  double wm = 0.0;
+  for (int64_t i = i0; i <= i1; ++i) wm += cl[i];
+  wm /= (double)(i1 - i0 + 1);
+  std::vector<double> ys;
+  crossings(wm, ys);
+  std::vector<double> keep;
+  for (double v : ys)
+    if (v >= a0 - 0.5 * T) keep.push_back(v);
+  if ((int64_t)keep.size() >= periods + 1) {
+    a0 = keep[keep.size() - periods - 1];
+    a1 = keep.back();
+    T = (a1 - a0) / periods;
+    i0 = (int64_t)std::ceil(a0);
+    i1 = (int64_t)std::floor(a1);
+  }
+  double lo = INFINITY, hi = -INFINITY, sd = 0.0;
+  for (int64_t i = i0; i <= i1; ++i) {
+    lo = std::min(lo, cl[i]);
+    hi = std::max(hi, cl[i]);
+    sd += cd[i];
+  }
+  out->mean_cd = sd / (double)(i1 - i0 + 1);
+  out->cl_amp = 0.5 * (hi - lo);
+  out->st = d / (T * u);
+  out->period = T;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Internal declarations shared by the gfx950 kernels and the host runtime of
+// liblbm.so.  Not part of the public ABI (see include/lbm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Wall modes, outlet modes: same values as the public enums.
+enum : int { kWallFreeSlip = 0, kWallPeriodic = 1, kWallNebb = 2, kWallMovingBB = 3 };
+enum : int { kOutletCopyAll = 0, kOutletCopyUnknown = 1 };
+
+// Force partials of one step live in a ring of kRing steps; a reduction
+// kernel folds them into the FP64 history every kRing steps (and at the end
+// of every lbm_step call).
+constexpr int kRing = 64;
+
+// Node flags inside the cylinder rectangle: bit 0 = solid node; bit k
+// (k = 1..8) = the pull source x - c_k of this fluid node is solid, so
+// population k arrives by half-way bounce-back instead of streaming.
+constexpr uint16_t kSolid = 1;
+
+struct Geometry {
+  int nx, ny;
+  int pitch;        // floats per row (>= nx, multiple of 64)
+  int64_t plane;    // floats per population plane (>= ny * pitch)
+  // cylinder rectangle [rx0, rx0+rw) x [ry0, ry0+rh) holding all solid nodes
+  // and all their fluid neighbours; empty (rw = rh = 0) without a cylinder
+  int rx0, ry0, rw, rh;
+  const uint16_t* flags;  // [rh][rw]
+};
+
+struct Physics {
+  float omega;     // 1/tau
+  float u_in;      // inlet velocity
+  float u_top, u_bot;
+  int wall, outlet_mode, x_periodic;
+};
+
+// Tiling of one launch.  A tile is tile_x consecutive nodes of tile_y
+// consecutive rows; one thread per x column loops over the tile's rows.
+struct Tiling {
+  int tile_x, tile_y;
+  int ntx, nty;          // tiles along x and y
+  int remap_xcd;         // 1: give each XCD a contiguous range of tiles
+  // tiles [fx0, fx0+fw) x [fy0, fy0+fh) write one FP64 force partial each
+  int fx0, fy0, fw, fh;
+};
+
+struct StepArgs {
+  const float* __restrict__ A;  // post-collision populations f*(t), 9 planes
+  float* __restrict__ B;        // receives f*(t+1)
+  Geometry g;
+  Physics p;
+  Tiling t;
+  double2* partial;             // this step's row of force partials [fw*fh]
+  int* bad;                     // watchdog: min ring slot with a bad density
+  int slot;                     // ring slot of this step
+};
+
+struct Variant {
+  const char* name;
+  int tile_x, tile_y, remap_xcd, nontemporal;
+};
+
+// Kernel launchers (lbm_kernels.hip).  All return the launch status.
+int num_variants();
+const Variant& variant(int v);  // 1-based
+hipError_t launch_step(const StepArgs& a, int v, hipStream_t s);
+hipError_t launch_force_reduce(const double2* partials, int nslots, int count, double* hist,
+                               int64_t cap, int64_t* dev_step, int* bad, int64_t* bad_step,
+                               hipStream_t s);
+hipError_t launch_init_equilibrium(float* f, const Geometry& g, double u, double amp,
+                                   hipStream_t s);
+hipError_t launch_fields(const float* f, const Geometry& g, float* rho, float* ux, float* uy,
+                         hipStream_t s);
+// dense [9][ny][nx] <-> pitched planes, with dtype 0 = f32, 1 = f64
+hipError_t launch_pack(const float* f, const Geometry& g, void* dense, int dtype, hipStream_t s);
+hipError_t launch_unpack(const void* dense, int dtype, const Geometry& g, float* f,
+                         hipStream_t s);
+hipError_t launch_fill_int(int* p, int value, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,138 @@
+"""Host-side checks of liblbm.so that need no GPU: exported symbols, parameter
+validation, the staircase geometry, the shedding statistics."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2605_02185_amd as lbm
+from lbm_inputs import WORKLOADS, channel, ensemble, truncated_window
+from paper_2605_02185_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            text = open(os.path.join(inc, fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(lbm_\w+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_function():
+    names = _declared_functions()
+    assert len(names) >= 19
+    raw = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in names if not hasattr(raw, n)]
+    assert not missing, missing
+
+
+def test_params_defaults_and_tau():
+    p = lbm.make_params(**WORKLOADS["cyl_d10"])
+    assert p.struct_size == ctypes.sizeof(_lib.Params)
+    assert lbm.tau_of(p) == pytest.approx(0.53)
+    q = lbm.make_params(**channel(40))
+    assert lbm.tau_of(q) == pytest.approx(0.56)  # Eqs. 16-17: 3 * 0.05 * 40 / 100 + 0.5
+    lbm.validate(p)
+    lbm.validate(q)
+
+
+@pytest.mark.parametrize(
+    "change",
+    [
+        dict(nx=2),
+        dict(ny=2),
+        dict(tau=0.5),
+        dict(tau=0.0, re=0.0),
+        dict(u_in=0.6),
+        dict(u_in=-0.01),
+        dict(wall=7),
+        dict(outlet_mode=3),
+        dict(cx2=4),  # cylinder touching the inlet
+        dict(cy2=2 * 208),  # cylinder touching the top wall
+        dict(hist_capacity=0),
+        dict(diameter=-1),
+        dict(perturb_amp=math.inf),
+    ],
+)
+def test_validation_rejects(change):
+    kw = dict(WORKLOADS["cyl_d10"])
+    kw.update(change)
+    p = lbm.make_params(**kw)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.validate(p)
+    assert e.value.status == _lib.ERR_INVALID_ARG
+    assert _lib.lib.lbm_last_error().decode()
+
+
+def test_validation_rejects_wrong_struct_size():
+    p = lbm.make_params(**WORKLOADS["cyl_d10"])
+    p.struct_size = 8
+    with pytest.raises(lbm.LbmError):
+        lbm.validate(p)
+
+
+@pytest.mark.parametrize("D", [8, 10, 13, 40])
+def test_geometry_matches_the_oracle_digitiser(D):
+    kw = channel(D)
+    mask, ns, nb, nl = lbm.geometry(lbm.make_params(**kw))
+    omask = oracle.digitise(oracle.OracleParams(**{k: v for k, v in kw.items()}))
+    assert np.array_equal(mask, omask)
+    assert ns == int(omask.sum())
+    if D == 10:
+        assert (ns, nb, nl) == (81, 48, 104)
+    if D == 40:
+        assert (ns, nb, nl) == (1257, 168, 392)
+
+
+def test_truncated_window_and_ensemble_are_valid():
+    lbm.validate(lbm.make_params(**truncated_window()))
+    cases = ensemble()
+    assert len(cases) == 64
+    ds = [c["diameter"] for c in cases]
+    res = [c["re"] for c in cases]
+    assert min(ds) >= 8 and max(ds) <= 32
+    assert min(res) >= 60 and max(res) <= 200
+    for c in cases:
+        lbm.validate(lbm.make_params(**c))
+    assert ensemble() == cases  # seeded
+
+
+@pytest.mark.parametrize("period", [97.3, 606.06, 4848.5])
+def test_shedding_stats_on_a_synthetic_sinusoid(period):
+    D, U = 40, 0.05
+    n = int(12 * period) + 7
+    t = np.arange(n)
+    cl = 0.33 * np.sin(2 * np.pi * t / period + 0.4) + 0.01
+    cd = 1.37 + 0.05 * np.sin(4 * np.pi * t / period + 1.0)
+    s = lbm.shedding_stats(cd, cl, D, U)
+    assert s["period"] == pytest.approx(period, rel=1e-4)
+    assert s["st"] == pytest.approx(D / (period * U), rel=1e-4)
+    assert s["cl_amp"] == pytest.approx(0.33, rel=2e-3)
+    assert s["mean_cd"] == pytest.approx(1.37, rel=2e-3)
+
+
+def test_shedding_stats_need_enough_periods():
+    with pytest.raises(lbm.RangeError):
+        lbm.shedding_stats(np.ones(500), np.zeros(500), 10, 0.1)
+
+
+def test_product_and_oracle_statistics_agree_on_a_noisy_signal():
+    rng = np.random.default_rng(5)
+    t = np.arange(20000)
+    cl = 0.3 * np.sin(2 * np.pi * t / 1234.5) + 1e-3 * rng.standard_normal(t.size)
+    cd = 1.3 + 0.02 * np.cos(4 * np.pi * t / 1234.5)
+    a = lbm.shedding_stats(cd, cl, 20, 0.05)
+    from oracle import stats as ostats
+
+    b = ostats.shedding(cd, cl, 20, 0.05)
+    for k in ("mean_cd", "cl_amp", "st"):
+        assert a[k] == pytest.approx(b[k], rel=1e-3)

@@ -1,0 +1,249 @@
+"""GPU parity: liblbm.so (gfx950 kernels, through the C ABI) against the FP64
+oracle on identical seeded inputs.
+
+Tolerance: |d rho|, |d u| and |d f*| <= 1e-5 after the stated number of steps
+(FP32 storage and arithmetic against FP64); force coefficients within 1e-3.
+Integer outputs (geometry, step counters, divergence step) must match exactly;
+repeated runs and kernel variants must match bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2605_02185_amd as lbm
+from lbm_inputs import WORKLOADS, channel, perturbed_populations
+
+pytestmark = pytest.mark.gpu
+
+# Table 1 weights, typed in from the paper (k = i - 1).
+WT = [4 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 36, 1 / 36, 1 / 36, 1 / 36]
+TOL = 1e-5
+ALL_WALLS = [lbm.WALL_FREE_SLIP, lbm.WALL_PERIODIC, lbm.WALL_NEBB, lbm.WALL_MOVING_BB]
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_kwargs(kw):
+    return {k: v for k, v in kw.items() if k != "hist_capacity"}
+
+
+def run_both(kw, steps, seed=None, amp=0.05):
+    """Run the GPU and the oracle from the same state; returns both objects
+    after `steps` steps plus the two force histories."""
+    note(f"parity case {kw} steps={steps} seed={seed}")
+    lat = lbm.Lattice(lbm.make_params(**kw))
+    o = oracle.Oracle(oracle.OracleParams(**_oracle_kwargs(kw)))
+    if seed is not None:
+        f0 = perturbed_populations(seed, kw["ny"], kw["nx"], WT, amp, dtype=np.float32)
+        lat.set_populations(f0)
+        o.set_fstar(f0.astype(np.float64))
+    lat.step(steps)
+    g = lat.forces() if steps else (np.zeros(0),) * 4
+    ofx, ofy, bad = o.step(steps)
+    assert bad == 0
+    return lat, o, g, (ofx, ofy)
+
+
+def compare_state(lat, o, solid=None, tol=TOL):
+    rho, ux, uy = lat.fields()
+    orho, oux, ouy = o.fields()
+    f = lat.get_populations(np.float64)
+    of = o.get_fstar()
+    fluid = np.ones_like(orho, dtype=bool) if solid is None else solid == 0
+    errs = {
+        "rho": np.abs(rho - orho)[fluid].max(),
+        "ux": np.abs(ux - oux)[fluid].max(),
+        "uy": np.abs(uy - ouy)[fluid].max(),
+        "f": np.abs(f - of)[:, fluid].max(),
+    }
+    note(f"  max errors {errs}")
+    for k, v in errs.items():
+        assert v <= tol, (k, v)
+    return errs
+
+
+# ------------------------------------------------------------------ boxes
+@pytest.mark.parametrize("nx,ny", [(3, 3), (64, 64), (517, 133)])
+def test_periodic_box_random_state(nx, ny):
+    kw = dict(nx=nx, ny=ny, tau=0.62, u_in=0.0, x_periodic=True, wall=lbm.WALL_PERIODIC)
+    lat, o, _, _ = run_both(kw, 40, seed=nx * 1000 + ny)
+    compare_state(lat, o)
+    f = lat.get_populations(np.float64)
+    m0 = perturbed_populations(nx * 1000 + ny, ny, nx, WT, 0.05, dtype=np.float32).astype(np.float64).sum()
+    assert abs(f.sum() - m0) / m0 < 1e-6  # mass, to FP32 accumulation
+
+
+@pytest.mark.parametrize("wall", [lbm.WALL_NEBB, lbm.WALL_MOVING_BB, lbm.WALL_FREE_SLIP])
+def test_x_periodic_channel_with_walls(wall):
+    kw = dict(nx=300, ny=37, tau=0.7, u_in=0.04, x_periodic=True, wall=wall, u_wall_bottom=0.0)
+    lat, o, _, _ = run_both(kw, 50, seed=7 + wall)
+    compare_state(lat, o)
+
+
+# --------------------------------------------------- cylinder channels
+@pytest.mark.parametrize("wall", ALL_WALLS)
+@pytest.mark.parametrize("outlet", [lbm.OUTLET_COPY_ALL, lbm.OUTLET_COPY_UNKNOWN])
+def test_channel_every_boundary_random_state(wall, outlet):
+    """D = 6 channel (246 x 126: one full and one ragged tile per row), every
+    wall mode and outlet mode, from a disturbed state."""
+    kw = dict(channel(6, u=0.06), tau=0.6, wall=wall, outlet_mode=outlet)
+    lat, o, (fx, fy, _, _), (ofx, ofy) = run_both(kw, 60, seed=100 + 10 * wall + outlet)
+    solid = oracle.digitise(oracle.OracleParams(**_oracle_kwargs(kw)))
+    compare_state(lat, o, solid)
+    assert np.abs(fx - ofx).max() < 1e-5 and np.abs(fy - ofy).max() < 1e-5
+
+
+@pytest.mark.parametrize("wall", ALL_WALLS)
+def test_uniform_flow_fixed_point(wall):
+    kw = dict(nx=300, ny=70, u_in=0.08, tau=0.7, wall=wall, perturb_amp=0.0)
+    lat, o, _, _ = run_both(kw, 20)
+    compare_state(lat, o, tol=1e-6)
+
+
+def test_minimal_channel():
+    kw = dict(nx=3, ny=3, u_in=0.05, tau=0.8, wall=lbm.WALL_NEBB)
+    lat, o, _, _ = run_both(kw, 10, seed=3)
+    compare_state(lat, o)
+
+
+def test_c1_fields_after_200_steps():
+    """410 x 210, D = 10, U = 0.1, tau = 0.53, free-slip: fields within 1e-5."""
+    kw = dict(WORKLOADS["cyl_d10"])
+    lat, o, (fx, fy, cd, cl), (ofx, ofy) = run_both(kw, 200)
+    solid = oracle.digitise(oracle.OracleParams(**_oracle_kwargs(kw)))
+    compare_state(lat, o, solid)
+    q = 0.5 * kw["u_in"] ** 2 * kw["diameter"]
+    assert np.abs(cd - ofx / q).max() < 1e-3
+    assert np.abs(cl - ofy / q).max() < 1e-3
+
+
+def test_c1_force_trace_2000_steps():
+    kw = dict(WORKLOADS["cyl_d10"])
+    lat, o, (fx, fy, cd, cl), (ofx, ofy) = run_both(kw, 2000)
+    q = 0.5 * kw["u_in"] ** 2 * kw["diameter"]
+    dcd = np.abs(cd - ofx / q).max()
+    dcl = np.abs(cl - ofy / q).max()
+    note(f"  max |dCd| {dcd:.2e} max |dCl| {dcl:.2e}")
+    assert dcd < 1e-3 and dcl < 1e-3
+
+
+@pytest.mark.parametrize("name", ["cyl_d80", "cyl_d160"])
+def test_full_size_two_steps_all_nodes(name):
+    """The benchmark's lattices in the benchmark's launch configuration:
+    two steps from a disturbed state, every node against the oracle."""
+    kw = dict(WORKLOADS[name])
+    lat, o, (fx, fy, _, _), (ofx, ofy) = run_both(kw, 2, seed=160, amp=0.02)
+    f = lat.get_populations(np.float64)
+    of = o.get_fstar()
+    solid = oracle.digitise(oracle.OracleParams(**_oracle_kwargs(kw)))
+    err = np.abs(f - of)[:, solid == 0].max()
+    note(f"  {name}: max |df*| {err:.2e}, forces {fx} vs {ofx}")
+    assert err <= TOL
+    assert np.abs(fx - ofx).max() < 1e-5 and np.abs(fy - ofy).max() < 1e-5
+
+
+# ----------------------------------------------- determinism and variants
+def _run_gpu(kw, steps, variant=0, seed=None):
+    lat = lbm.Lattice(lbm.make_params(**kw))
+    if variant:
+        lat.set_variant(variant)
+    if seed is not None:
+        lat.set_populations(perturbed_populations(seed, kw["ny"], kw["nx"], WT, 0.05, dtype=np.float32))
+    lat.step(steps)
+    return lat.get_populations(), lat.forces()
+
+
+@pytest.mark.parametrize("kw", [dict(WORKLOADS["cyl_d10"]),
+                                dict(nx=517, ny=133, tau=0.6, u_in=0.0, x_periodic=True, wall=lbm.WALL_PERIODIC)])
+def test_variants_and_repeats_are_bitwise_identical(kw):
+    seed = None if "diameter" in kw else 9
+    ref_f, ref_forces = _run_gpu(kw, 37, 0, seed)
+    for v in range(1, lbm.num_variants() + 1):
+        f, forces = _run_gpu(kw, 37, v, seed)
+        note(f"  variant {lbm.variant_name(v)}")
+        assert np.array_equal(f, ref_f), v
+        for a, b in zip(forces, ref_forces):
+            if a is not None:
+                assert np.array_equal(a, b), v
+
+
+def test_checkpoint_round_trip_is_bitwise():
+    kw = dict(WORKLOADS["cyl_d10"])
+    a = lbm.Lattice(lbm.make_params(**kw))
+    a.step(150)
+    mid = a.get_populations()
+    a.step(70)
+    end = a.get_populations()
+    fa = a.forces(151, 70)
+    b = lbm.Lattice(lbm.make_params(**kw))
+    b.set_populations(mid)
+    b.step(70)
+    assert np.array_equal(b.get_populations(), end)
+    assert np.array_equal(b.forces(1, 70)[0], fa[0])
+
+
+def test_force_ring_wraps_and_reports_range():
+    kw = dict(WORKLOADS["cyl_d10"], hist_capacity=100)
+    a = lbm.Lattice(lbm.make_params(**kw))
+    a.step(250)
+    fx, fy, _, _ = a.forces(151, 100)
+    b = lbm.Lattice(lbm.make_params(**dict(WORKLOADS["cyl_d10"])))
+    b.step(250)
+    gx, gy, _, _ = b.forces(151, 100)
+    assert np.array_equal(fx, gx) and np.array_equal(fy, gy)
+    with pytest.raises(lbm.RangeError):
+        a.forces(150, 1)
+    with pytest.raises(lbm.RangeError):
+        a.forces(250, 2)
+    assert a.forces(251, 0)[0].size == 0
+    a.step(0)
+    assert a.t == 250
+
+
+# --------------------------------------------------------- failure paths
+def test_divergence_is_reported():
+    kw = dict(nx=82, ny=42, diameter=2, u_in=0.2, tau=0.5001)
+    lat = lbm.Lattice(lbm.make_params(**kw))
+    lat.step(3000)
+    with pytest.raises(lbm.DivergedError):
+        lat.sync()
+    s = lat.diverged_step()
+    o = oracle.Oracle(oracle.OracleParams(**kw))
+    _, _, obad = o.step(3000)
+    note(f"  diverged at GPU step {s}, oracle step {obad}")
+    assert s > 0 and obad > 0
+
+
+def test_nan_state_is_reported_at_step_one():
+    kw = dict(WORKLOADS["cyl_d10"])
+    lat = lbm.Lattice(lbm.make_params(**kw))
+    f = lat.get_populations()
+    f[3, 100, 200] = np.nan
+    lat.set_populations(f)
+    lat.step(5)
+    assert lat.diverged_step() == 1
+    with pytest.raises(lbm.DivergedError):
+        lat.forces(1, 5)
+
+
+def test_device_buffers_round_trip():
+    import torch
+
+    kw = dict(WORKLOADS["cyl_d10"])
+    lat = lbm.Lattice(lbm.make_params(**kw))
+    lat.step(10)
+    t = torch.empty((9, kw["ny"], kw["nx"]), dtype=torch.float64, device="cuda")
+    lat.get_populations_device(t)
+    host = lat.get_populations(np.float64)
+    assert np.array_equal(t.cpu().numpy(), host)
+    rho = torch.empty((kw["ny"], kw["nx"]), dtype=torch.float32, device="cuda")
+    lat.fields_device(rho, None, None)
+    assert np.array_equal(rho.cpu().numpy(), lat.fields()[0])
+    t32 = t.float()
+    lat.set_populations_device(t32)
+    assert np.array_equal(lat.get_populations(), t32.cpu().numpy())
