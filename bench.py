@@ -1,0 +1,191 @@
+"""Throughput benchmark of the D2Q9 BGK solver on one MI355X.
+
+One step = one pass of the whole hot path over the lattice: pull streaming,
+half-way bounce-back on the cylinder, wall/outlet/inlet corrections, BGK
+collision and the FP64 momentum-exchange force (plus its fixed-order history
+reduction every 64 steps).  The default workload is the D = 160 cylinder
+channel (6560 x 3360 = 22.0 M nodes, Re = 100, U = 0.05, free-slip walls),
+whose two population buffers (1.6 GB) are far larger than the 256 MB
+Infinity Cache, so the step is bound by HBM bandwidth.
+
+Prints one JSON line:
+  value      MLUPS = nx * ny * steps / time / 1e6 (all nodes)
+  roofline   algorithmic bytes (72 B per node update: 9 FP32 loads + 9 FP32
+             stores) per step over the measured average step time, against
+             the 8 TB/s HBM3E peak; `traffic` comes from the committed
+             rocprofv3 FETCH_SIZE/WRITE_SIZE summary when it was taken on the
+             current kernel source, else null
+  cpu_baseline  the FP64 oracle timed on this host on a bounded sample
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BYTES_PER_NODE = 72  # 9 FP32 loads + 9 FP32 stores per node update
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_kernel.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2605_02185_amd", "csrc", "lbm_kernels.hip")
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def stored_traffic(workload: str):
+    """HBM bytes per step from the committed counter summary, if it was taken
+    on the current kernel source and workload."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_sha256_16") != kernel_hash() or d.get("workload") != workload:
+        return None
+    return d.get("bytes_per_step")
+
+
+def copy_ceiling(torch, nbytes: int, reps: int = 20) -> float:
+    """GB/s of torch's device-to-device copy of nbytes (read + write counted)."""
+    n = nbytes // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(w: dict, budget_s: float) -> dict:
+    """The FP64 oracle, as it stands, on this host: steps of the same lattice
+    until about budget_s seconds of stepping have elapsed."""
+    import oracle
+
+    o = oracle.Oracle(oracle.OracleParams(**w))
+    o.step(1)  # first touch of the buffers
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        o.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 200:
+            break
+    nodes = w["nx"] * w["ny"]
+    o.close()
+    return {
+        "value": nodes * steps / el / 1e6,
+        "unit": "MLUPS",
+        "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": f"{steps} steps of the {w['nx']}x{w['ny']} lattice ({el:.1f} s, FP64, OpenMP)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=400)
+    ap.add_argument("--workload", default="cyl_d160")
+    ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-copy", action="store_true", help="skip the copy-ceiling reference")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+              "multi-GPU slab decomposition is design-only", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2605_02185_amd as lbm
+    from lbm_inputs import WORKLOADS
+
+    torch.cuda.set_device(0)
+    w = dict(WORKLOADS[args.workload])
+    p = lbm.make_params(**w)
+    nodes = w["nx"] * w["ny"]
+    stream = torch.cuda.current_stream()
+    lat = lbm.Lattice(p, stream=stream.cuda_stream)
+    if args.variant:
+        lat.set_variant(args.variant)
+    lat.step(args.warmup)
+    lat.sync()
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    lat.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat.sync()  # raises if the run diverged
+    gpu_ms = e0.elapsed_time(e1)
+    ms_per_step = gpu_ms / args.steps
+    mlups = nodes * args.steps / (gpu_ms * 1e-3) / 1e6
+    fluid = nodes - lbm.geometry(p)[1]
+
+    achieved = BYTES_PER_NODE * nodes / (ms_per_step * 1e-3) / 1e9
+    traffic = stored_traffic(args.workload)
+    roof = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": PEAK_HBM_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / PEAK_HBM_GBS, 4),
+        "traffic": traffic,
+        "algorithmic_bytes_per_step": BYTES_PER_NODE * nodes,
+        "kernel": "step_kernel",
+    }
+    out = {
+        "metric": "D2Q9 MLUPS & % HBM roofline",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "nx": w["nx"], "ny": w["ny"], "diameter": w["diameter"], "u_in": w["u_in"],
+            "re": w["re"], "tau": round(lbm.tau_of(p), 6), "wall": "free-slip",
+            "outlet": "copy-all", "variant": lbm.variant_name(args.variant or 1),
+        },
+        "roofline": roof,
+        "mlups_fluid": round(fluid * args.steps / (gpu_ms * 1e-3) / 1e6, 1),
+        "wall_s": round(wall, 3),
+    }
+    if not args.no_copy:
+        cc = copy_ceiling(torch, 9 * nodes * 4)
+        out["copy_ceiling"] = {"GB/s": round(cc, 1), "frac_of_copy": round(achieved / cc, 4)}
+    lat.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

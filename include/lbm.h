@@ -139,8 +139,11 @@ lbm_status lbm_forces(lbm_ctx* ctx, int64_t first, int64_t count, double* fx, do
 lbm_status lbm_fields(lbm_ctx* ctx, float* rho, float* ux, float* uy, int on_device);
 
 /* State exchange, layout [9][ny][nx].  The state between steps is the set of
- * post-collision populations f*(x, t) (what streams next).  dtype 0 = float32,
- * 1 = float64 (converted on the device).  Setting the state keeps the step
+ * post-collision populations f*(x, t) (what streams next).  The device holds
+ * them in FP32 as deviations f*_k - w_k from the rest equilibrium; these
+ * calls exchange the unshifted f*_k.  dtype 0 = float32 (rounded once),
+ * 1 = float64 (holds the stored state exactly, so a float64 get/set round
+ * trip restores the state bit for bit).  Setting the state keeps the step
  * counter and force history; the next step streams the given populations. */
 lbm_status lbm_get_populations(lbm_ctx* ctx, void* buf, int dtype, int on_device);
 lbm_status lbm_set_populations(lbm_ctx* ctx, const void* buf, int dtype, int on_device);

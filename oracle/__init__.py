@@ -84,6 +84,7 @@ def _load():
     lib.oracle_digitise.restype = ctypes.c_long
     lib.oracle_tau.argtypes = [P]
     lib.oracle_tau.restype = ctypes.c_double
+    lib.oracle_threads.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -132,6 +133,11 @@ def digitise(p: OracleParams) -> np.ndarray:
     cp = p._c()
     lib.oracle_digitise(ctypes.byref(cp), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
     return out
+
+
+def threads() -> int:
+    """OpenMP threads used by the oracle's parallel loops."""
+    return _load().oracle_threads()
 
 
 def tau_of(p: OracleParams) -> float:

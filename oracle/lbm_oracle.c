@@ -21,6 +21,7 @@
 #include "lbm_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -414,3 +415,5 @@ void oracle_set_fstar(oracle* o, const double* in) {
   oracle_set_f(o, in);
   o->state_is_post = 1;
 }
+
+int oracle_threads(void) { return omp_get_max_threads(); }

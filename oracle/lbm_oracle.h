@@ -87,6 +87,9 @@ void oracle_set_f(oracle* o, const double* in);
 void oracle_get_fstar(const oracle* o, double* out);
 void oracle_set_fstar(oracle* o, const double* in);
 
+/* OpenMP threads the oracle's parallel loops use. */
+int oracle_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

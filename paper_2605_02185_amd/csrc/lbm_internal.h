@@ -29,6 +29,11 @@ struct Geometry {
   // and all their fluid neighbours; empty (rw = rh = 0) without a cylinder
   int rx0, ry0, rw, rh;
   const uint16_t* flags;  // [rh][rw]
+  // [rh][rw]: position of a fluid node with bounce-back links in the list of
+  // such nodes (row-major order), -1 elsewhere; fixes where each node's FP64
+  // force contribution goes, so the sum order never depends on the tiling
+  const int32_t* link_index;
+  int n_link_nodes;
 };
 
 struct Physics {
@@ -39,13 +44,11 @@ struct Physics {
 };
 
 // Tiling of one launch.  A tile is tile_x consecutive nodes of tile_y
-// consecutive rows; one thread per x column loops over the tile's rows.
+// consecutive rows, handled by one block of 256 threads.
 struct Tiling {
   int tile_x, tile_y;
   int ntx, nty;          // tiles along x and y
   int remap_xcd;         // 1: give each XCD a contiguous range of tiles
-  // tiles [fx0, fx0+fw) x [fy0, fy0+fh) write one FP64 force partial each
-  int fx0, fy0, fw, fh;
 };
 
 struct StepArgs {
@@ -54,21 +57,23 @@ struct StepArgs {
   Geometry g;
   Physics p;
   Tiling t;
-  double2* partial;             // this step's row of force partials [fw*fh]
+  double2* partial;             // this step's force contributions [n_link_nodes]
   int* bad;                     // watchdog: min ring slot with a bad density
   int slot;                     // ring slot of this step
 };
 
 struct Variant {
   const char* name;
-  int tile_x, tile_y, remap_xcd, nontemporal;
+  int tile_x, tile_y;  // nodes along x (= 256 * vx) and rows per tile
+  int vx;              // consecutive nodes per lane on the bulk path
+  int remap_xcd, nontemporal;
 };
 
 // Kernel launchers (lbm_kernels.hip).  All return the launch status.
 int num_variants();
 const Variant& variant(int v);  // 1-based
 hipError_t launch_step(const StepArgs& a, int v, hipStream_t s);
-hipError_t launch_force_reduce(const double2* partials, int nslots, int count, double* hist,
+hipError_t launch_force_reduce(const double2* partials, int nnodes, int count, double* hist,
                                int64_t cap, int64_t* dev_step, int* bad, int64_t* bad_step,
                                hipStream_t s);
 hipError_t launch_init_equilibrium(float* f, const Geometry& g, double u, double amp,

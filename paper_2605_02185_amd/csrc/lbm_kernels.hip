@@ -1,7 +1,12 @@
 // gfx950 kernels of the D2Q9 BGK cylinder-flow solver (arXiv 2605.02185).
 //
 // State between steps: post-collision populations f*(x, t) in 9 SoA planes,
-// rows padded to a multiple of 64 floats.  One launch of step_kernel turns
+// rows padded to a multiple of 64 floats, stored shifted by the rest
+// equilibrium as h_k = f*_k - w_k (FP32).  The deviations are two orders of
+// magnitude smaller than f itself, so FP32 rounding errors shrink by the same
+// factor (shifted storage, Skordos 1993).  Every population formula of the
+// boundary treatments pairs directions of equal weight, so it reads the same
+// on h as on f; only densities carry the explicit 1 = sum of the weights.  One launch of step_kernel turns
 // buffer A = f*(t) into buffer B = f*(t+1) node by node:
 //   1. pull: f_k(x) = f*_k(x - c_k)                               (Eq. 2, LHS)
 //      half-way bounce-back where x - c_k is solid: f_k(x) = f*_opp(k)(x)
@@ -30,17 +35,21 @@ constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 constexpr float W0 = 4.0f / 9.0f, W1 = 1.0f / 9.0f, W2 = 1.0f / 36.0f;
 
-// Eq. 4 then Eqs. 2-3 on the nine streamed and corrected populations g;
-// writes f* to B at element offset o of each plane.  Flags a density that is
-// non-finite or outside (0, 10).
-template <bool NT>
-__device__ __forceinline__ void collide_store(const float (&g)[9], float omega, float* __restrict__ B,
-                                              uint32_t plane, uint32_t o, bool& bad) {
-  const float rho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+// Eq. 4 then Eqs. 2-3 on the nine streamed and corrected deviations
+// g_k = f_k - w_k, giving the post-collision deviations out.  With
+// drho = rho - 1 = sum g_k and j = sum c_k g_k:
+//   f_eq,k - w_k = w_k [drho + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)].
+// Flags a density that is non-finite or outside (0, 10).  Contraction is
+// off and every fused multiply-add is written out, so that each kernel
+// variant (scalar or vector bulk path, general path) rounds identically.
+__device__ __forceinline__ void collide(const float (&g)[9], float omega, float (&out)[9], bool& bad) {
+#pragma clang fp contract(off)
+  const float drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+  const float rho = 1.0f + drho;
   const float ir = 1.0f / rho;
   const float ux = (((g[1] - g[3]) + (g[5] - g[7])) + (g[8] - g[6])) * ir;
   const float uy = (((g[2] - g[4]) + (g[5] - g[7])) + (g[6] - g[8])) * ir;
-  const float usq = 1.5f * (ux * ux + uy * uy);
+  const float usq = 1.5f * __fmaf_rn(ux, ux, uy * uy);
   bad |= !(rho > 0.0f && rho < 10.0f);
   float cu[9];
   cu[0] = 0.0f;
@@ -55,14 +64,30 @@ __device__ __forceinline__ void collide_store(const float (&g)[9], float omega, 
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     const float w = k == 0 ? W0 : (k < 5 ? W1 : W2);
-    const float feq = w * rho * (1.0f - usq + cu[k] * (3.0f + 4.5f * cu[k]));
-    const float v = g[k] + omega * (feq - g[k]);
+    const float poly = __fmaf_rn(cu[k], __fmaf_rn(4.5f, cu[k], 3.0f), -usq);
+    const float feq = w * __fmaf_rn(rho, poly, drho);
+    out[k] = __fmaf_rn(omega, feq - g[k], g[k]);
+  }
+}
+
+template <bool NT>
+__device__ __forceinline__ void store9(float* __restrict__ B, uint32_t plane, uint32_t o, const float (&v)[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
     float* dst = B + k * plane + o;
     if (NT)
-      __builtin_nontemporal_store(v, dst);
+      __builtin_nontemporal_store(v[k], dst);
     else
-      *dst = v;
+      *dst = v[k];
   }
+}
+
+template <bool NT>
+__device__ __forceinline__ void collide_store(const float (&g)[9], float omega, float* __restrict__ B,
+                                              uint32_t plane, uint32_t o, bool& bad) {
+  float out[9];
+  collide(g, omega, out, bad);
+  store9<NT>(B, plane, o, out);
 }
 
 __device__ __forceinline__ uint16_t node_flags(const Geometry& g, int x, int y) {
@@ -118,13 +143,13 @@ __device__ __forceinline__ void wall_bc(const StepArgs& a, int x, int y, float (
       const float U = top ? a.p.u_top : a.p.u_bot;
       const float d13 = 0.5f * (g[1] - g[3]);
       if (top) {
-        const float rw = (g[0] + g[1] + g[3]) + 2.0f * (g[2] + g[5] + g[6]);
+        const float rw = 1.0f + ((g[0] + g[1] + g[3]) + 2.0f * (g[2] + g[5] + g[6]));
         const float m = 0.5f * rw * U;
         g[4] = g[2];
         g[7] = g[5] + d13 - m;
         g[8] = g[6] - d13 + m;
       } else {
-        const float rw = (g[0] + g[1] + g[3]) + 2.0f * (g[4] + g[7] + g[8]);
+        const float rw = 1.0f + ((g[0] + g[1] + g[3]) + 2.0f * (g[4] + g[7] + g[8]));
         const float m = 0.5f * rw * U;
         g[2] = g[4];
         g[5] = g[7] - d13 + m;
@@ -137,7 +162,7 @@ __device__ __forceinline__ void wall_bc(const StepArgs& a, int x, int y, float (
       float fs[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) fs[k] = load(a.A, a.g, k, x, y);
-      const float rho = ((fs[0] + fs[1]) + (fs[2] + fs[3])) + ((fs[4] + fs[5]) + (fs[6] + fs[7])) + fs[8];
+      const float rho = 1.0f + (((fs[0] + fs[1]) + (fs[2] + fs[3])) + ((fs[4] + fs[5]) + (fs[6] + fs[7])) + fs[8]);
       const float m = rho * U * (1.0f / 6.0f);
       if (top) {
         g[4] = fs[2];
@@ -164,8 +189,7 @@ __device__ __forceinline__ void gather(const StepArgs& a, int x, int y, uint16_t
 }
 
 template <bool NT>
-__device__ __forceinline__ void general_node(const StepArgs& a, int x, int y, double& Fx, double& Fy,
-                                          bool& bad) {
+__device__ __forceinline__ void general_node(const StepArgs& a, int x, int y, bool& bad) {
   const int nx = a.g.nx, ny = a.g.ny;
   const uint32_t o = (uint32_t)y * (uint32_t)a.g.pitch + (uint32_t)x;
   const uint32_t P = (uint32_t)a.g.plane;
@@ -203,10 +227,10 @@ __device__ __forceinline__ void general_node(const StepArgs& a, int x, int y, do
       for (int k = 0; k < 9; ++k) {
         const float w = k == 0 ? W0 : (k < 5 ? W1 : W2);
         const float cu = (float)CX[k] * U;
-        g[k] = w * (1.0f - usq + cu * (3.0f + 4.5f * cu));
+        g[k] = w * (cu * (3.0f + 4.5f * cu) - usq);
       }
-    } else {  // Zou-He velocity inlet, u = (U, 0)
-      const float rho = ((g[0] + g[2]) + g[4] + 2.0f * ((g[3] + g[6]) + g[7])) / (1.0f - U);
+    } else {  // Zou-He velocity inlet, u = (U, 0); the known weights sum to 1
+      const float rho = (1.0f + ((g[0] + g[2]) + g[4] + 2.0f * ((g[3] + g[6]) + g[7]))) / (1.0f - U);
       const float d24 = 0.5f * (g[2] - g[4]);
       g[1] = g[3] + (2.0f / 3.0f) * rho * U;
       g[5] = g[7] - d24 + rho * U * (1.0f / 6.0f);
@@ -216,12 +240,16 @@ __device__ __forceinline__ void general_node(const StepArgs& a, int x, int y, do
   if (fl >> 1) {
     // Eq. 14: each bounced population g_k = f*_opp(k)(x) left along c_opp(k)
     // and came back along c_k, giving the body 2 c_opp(k) f*_opp(k).
+    double Fx = 0.0, Fy = 0.0;
 #pragma unroll
     for (int k = 1; k < 9; ++k)
       if ((fl >> k) & 1) {
-        Fx -= 2.0 * (double)CX[k] * (double)g[k];
-        Fy -= 2.0 * (double)CY[k] * (double)g[k];
+        const double fk = (double)g[k] + (k < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+        Fx -= 2.0 * (double)CX[k] * fk;
+        Fy -= 2.0 * (double)CY[k] * fk;
       }
+    const int idx = a.g.link_index[(y - a.g.ry0) * a.g.rw + (x - a.g.rx0)];
+    a.partial[idx] = make_double2(Fx, Fy);
   }
   collide_store<NT>(g, a.p.omega, a.B, P, o, bad);
 }
@@ -244,6 +272,79 @@ __device__ __forceinline__ void bulk_node(const StepArgs& a, int x, int y, bool&
   collide_store<NT>(g, a.p.omega, a.B, P, o, bad);
 }
 
+template <int VX>
+struct Vec;
+template <>
+struct Vec<2> {
+  typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec<4> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+
+// VX consecutive interior nodes x0 .. x0+VX-1 of one row per lane, with every
+// lane of the wave on the bulk path.  Each population plane is read with one
+// aligned VX-wide load per lane; the one value a lane needs from outside its
+// own span (x0-1 for the eastward-moving E, NE, SE, x0+VX for the westward
+// W, NW, SW) comes from the neighbouring lane by a cross-lane shuffle, and
+// only lanes 0 and 63 read it from memory.
+template <int VX, bool NT>
+__device__ __forceinline__ void bulk_vec(const StepArgs& a, int x0, int y, bool& bad) {
+  typedef typename Vec<VX>::type V;
+  const float* __restrict__ A = a.A;
+  const uint32_t P = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
+  const uint32_t o = (uint32_t)y * Wp + (uint32_t)x0;
+  const uint32_t on = o - Wp, os = o + Wp;  // rows y-1 and y+1
+  const V r = *(const V*)(A + o);
+  const V n = *(const V*)(A + 2 * P + on);
+  const V s = *(const V*)(A + 4 * P + os);
+  const V e = *(const V*)(A + 1 * P + o);
+  const V ne = *(const V*)(A + 5 * P + on);
+  const V se = *(const V*)(A + 8 * P + os);
+  const V w = *(const V*)(A + 3 * P + o);
+  const V nw = *(const V*)(A + 6 * P + on);
+  const V sw = *(const V*)(A + 7 * P + os);
+  const int lane = (int)(threadIdx.x & 63);
+  float e_in = __shfl_up(e[VX - 1], 1), ne_in = __shfl_up(ne[VX - 1], 1), se_in = __shfl_up(se[VX - 1], 1);
+  float w_in = __shfl_down(w[0], 1), nw_in = __shfl_down(nw[0], 1), sw_in = __shfl_down(sw[0], 1);
+  if (lane == 0) {
+    e_in = A[1 * P + o - 1];
+    ne_in = A[5 * P + on - 1];
+    se_in = A[8 * P + os - 1];
+  }
+  if (lane == 63) {
+    w_in = A[3 * P + o + VX];
+    nw_in = A[6 * P + on + VX];
+    sw_in = A[7 * P + os + VX];
+  }
+  V out[9];
+#pragma unroll
+  for (int j = 0; j < VX; ++j) {
+    float g[9], f[9];
+    g[0] = r[j];
+    g[2] = n[j];
+    g[4] = s[j];
+    g[1] = j == 0 ? e_in : e[j > 0 ? j - 1 : 0];
+    g[5] = j == 0 ? ne_in : ne[j > 0 ? j - 1 : 0];
+    g[8] = j == 0 ? se_in : se[j > 0 ? j - 1 : 0];
+    g[3] = j == VX - 1 ? w_in : w[j < VX - 1 ? j + 1 : 0];
+    g[6] = j == VX - 1 ? nw_in : nw[j < VX - 1 ? j + 1 : 0];
+    g[7] = j == VX - 1 ? sw_in : sw[j < VX - 1 ? j + 1 : 0];
+    collide(g, a.p.omega, f, bad);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) out[k][j] = f[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    V* dst = (V*)(a.B + k * P + o);
+    if (NT)
+      __builtin_nontemporal_store(out[k], dst);
+    else
+      *dst = out[k];
+  }
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs (block id mod 8); hand
 // each XCD a contiguous range of tiles so that neighbouring tiles, which
 // share halo cache lines, meet in the same L2.
@@ -253,95 +354,78 @@ __device__ __forceinline__ int remap_xcd(int id, int n) {
   return xcd * per + min(xcd, rem) + local;
 }
 
-// FP64 sum of (fx, fy) over the block; thread 0 gets the result.
-__device__ __forceinline__ double2 block_sum(double fx, double fy) {
-  __shared__ double2 part[16];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    fx += __shfl_xor(fx, off);
-    fy += __shfl_xor(fy, off);
-  }
-  const int wave = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) part[wave] = make_double2(fx, fy);
-  __syncthreads();
-  double2 s = make_double2(0.0, 0.0);
-  if (threadIdx.x == 0)
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-      s.x += part[w].x;
-      s.y += part[w].y;
-    }
-  return s;
-}
-
-template <int TY, bool NT>
+// One tile = tile_x = 256 * VX consecutive nodes of TY rows; lane t of the
+// block owns nodes x0 .. x0+VX-1 with x0 = tile origin + VX t.
+template <int TY, int VX, bool NT>
 __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
   const int ntiles = a.t.ntx * a.t.nty;
   const int tile = a.t.remap_xcd ? remap_xcd((int)blockIdx.x, ntiles) : (int)blockIdx.x;
   const int bx = tile % a.t.ntx, by = tile / a.t.ntx;
   const int nx = a.g.nx, ny = a.g.ny;
-  const int x = bx * a.t.tile_x + (int)threadIdx.x;
-  double Fx = 0.0, Fy = 0.0;
+  const int x0 = bx * a.t.tile_x + (int)threadIdx.x * VX;
   bool bad = false;
 #pragma unroll
   for (int r = 0; r < TY; ++r) {
     const int y = by * TY + r;
-    const bool active = x < nx && y < ny;
-    const bool special =
-        active && (x == 0 || x == nx - 1 || y == 0 || y == ny - 1 || in_rect(a.g, x, y));
+    const bool active = x0 < nx && y < ny;
+    const bool rect = (unsigned)(y - a.g.ry0) < (unsigned)a.g.rh && x0 + VX - 1 >= a.g.rx0 &&
+                      x0 < a.g.rx0 + a.g.rw;
+    const bool special = active && (x0 == 0 || x0 + VX - 1 >= nx - 1 || y == 0 || y == ny - 1 || rect);
     if (__any(special)) {
-      if (active) general_node<NT>(a, x, y, Fx, Fy, bad);
+#pragma unroll
+      for (int j = 0; j < VX; ++j)
+        if (active && x0 + j < nx) general_node<NT>(a, x0 + j, y, bad);
     } else if (active) {
-      bulk_node<NT>(a, x, y, bad);
+      if constexpr (VX == 1)
+        bulk_node<NT>(a, x0, y, bad);
+      else
+        bulk_vec<VX, NT>(a, x0, y, bad);
     }
   }
   if (bad) atomicMin(a.bad, a.slot);
-  const unsigned fxr = (unsigned)(bx - a.t.fx0), fyr = (unsigned)(by - a.t.fy0);
-  if (fxr < (unsigned)a.t.fw && fyr < (unsigned)a.t.fh) {
-    const double2 s = block_sum(Fx, Fy);
-    if (threadIdx.x == 0) a.partial[fyr * a.t.fw + fxr] = s;
+}
+
+// Folds row blockIdx.x of the per-node force contributions into the FP64
+// history at step *dev_step + blockIdx.x.  The order is fixed: thread t sums
+// nodes t, t+256, ... in turn, each wave reduces its 64 sums by a butterfly
+// of shuffles, and thread 0 adds the four wave sums in wave order.
+__global__ __launch_bounds__(256) void force_reduce_kernel(const double2* __restrict__ partials,
+                                                           int nnodes, double* hist, int64_t cap,
+                                                           const int64_t* dev_step) {
+  __shared__ double2 wsum[4];
+  const int j = blockIdx.x;
+  double sx = 0.0, sy = 0.0;
+  for (int i = threadIdx.x; i < nnodes; i += 256) {
+    const double2 v = partials[(int64_t)j * nnodes + i];
+    sx += v.x;
+    sy += v.y;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    sx += __shfl_xor(sx, off);
+    sy += __shfl_xor(sy, off);
+  }
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = make_double2(sx, sy);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double fx = (wsum[0].x + wsum[1].x) + (wsum[2].x + wsum[3].x);
+    const double fy = (wsum[0].y + wsum[1].y) + (wsum[2].y + wsum[3].y);
+    const int64_t s = (*dev_step + j) % cap;
+    hist[2 * s] = fx;
+    hist[2 * s + 1] = fy;
   }
 }
 
-// Folds `count` rows of force partials into the FP64 history in a fixed
-// order, advances the device step counter and converts the watchdog slot
-// into an absolute step.  One block.
-__global__ __launch_bounds__(256) void force_reduce_kernel(const double2* __restrict__ partials,
-                                                           int nslots, int count, double* hist,
-                                                           int64_t cap, int64_t* dev_step, int* bad,
-                                                           int64_t* bad_step) {
-  __shared__ double2 sh[256];
+// Runs after force_reduce_kernel: advances the device step counter by
+// `count` and turns the watchdog's ring slot into an absolute step.
+__global__ void advance_kernel(int count, int64_t* dev_step, int* bad, int64_t* bad_step) {
   const int64_t base = *dev_step;
-  for (int j = 0; j < count; ++j) {
-    double sx = 0.0, sy = 0.0;
-    for (int i = threadIdx.x; i < nslots; i += 256) {
-      const double2 v = partials[(int64_t)j * nslots + i];
-      sx += v.x;
-      sy += v.y;
-    }
-    sh[threadIdx.x] = make_double2(sx, sy);
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) {
-        sh[threadIdx.x].x += sh[threadIdx.x + w].x;
-        sh[threadIdx.x].y += sh[threadIdx.x + w].y;
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      const int64_t s = (base + j) % cap;
-      hist[2 * s] = sh[0].x;
-      hist[2 * s + 1] = sh[0].y;
-    }
-    __syncthreads();
+  const int b = *bad;
+  if (b != INT_MAX) {
+    if (*bad_step == 0) *bad_step = base + b + 1;
+    *bad = INT_MAX;
   }
-  if (threadIdx.x == 0) {
-    const int b = *bad;
-    if (b != INT_MAX) {
-      if (*bad_step == 0) *bad_step = base + b + 1;
-      *bad = INT_MAX;
-    }
-    *dev_step = base + count;
-  }
+  *dev_step = base + count;
 }
 
 __global__ void init_eq_kernel(float* f, Geometry g, double u, double amp) {
@@ -352,7 +436,7 @@ __global__ void init_eq_kernel(float* f, Geometry g, double u, double amp) {
   for (int k = 0; k < 9; ++k) {
     const double w = k == 0 ? 4.0 / 9.0 : (k < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
     const double cu = CX[k] * u + CY[k] * v;
-    f[(int64_t)k * g.plane + (int64_t)y * g.pitch + x] = (float)(w * (1.0 - usq + cu * (3.0 + 4.5 * cu)));
+    f[(int64_t)k * g.plane + (int64_t)y * g.pitch + x] = (float)(w * (cu * (3.0 + 4.5 * cu) - usq));
   }
 }
 
@@ -364,7 +448,7 @@ __global__ void fields_kernel(const float* __restrict__ f, Geometry g, float* rh
   if (!(node_flags(g, x, y) & kSolid)) {
     float h[9];
     for (int k = 0; k < 9; ++k) h[k] = f[(int64_t)k * g.plane + (int64_t)y * g.pitch + x];
-    r = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
+    r = 1.0f + (((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8]);
     u = (((h[1] - h[3]) + (h[5] - h[7])) + (h[8] - h[6])) / r;
     v = (((h[2] - h[4]) + (h[5] - h[7])) + (h[6] - h[8])) / r;
   }
@@ -373,33 +457,40 @@ __global__ void fields_kernel(const float* __restrict__ f, Geometry g, float* rh
   if (uy) uy[i] = v;
 }
 
+__device__ __forceinline__ double weight(int k) {
+  return k == 0 ? 4.0 / 9.0 : (k < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+
 __global__ void pack_kernel(const float* __restrict__ f, Geometry g, void* dense, int dtype) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, k = blockIdx.z;
   if (x >= g.nx || y >= g.ny) return;
-  const float v = f[(int64_t)k * g.plane + (int64_t)y * g.pitch + x];
+  const double v = (double)f[(int64_t)k * g.plane + (int64_t)y * g.pitch + x] + weight(k);
   const int64_t i = ((int64_t)k * g.ny + y) * g.nx + x;
   if (dtype == 0)
-    ((float*)dense)[i] = v;
+    ((float*)dense)[i] = (float)v;
   else
-    ((double*)dense)[i] = (double)v;
+    ((double*)dense)[i] = v;
 }
 
 __global__ void unpack_kernel(const void* dense, int dtype, Geometry g, float* f) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, k = blockIdx.z;
   if (x >= g.nx || y >= g.ny) return;
   const int64_t i = ((int64_t)k * g.ny + y) * g.nx + x;
-  const float v = dtype == 0 ? ((const float*)dense)[i] : (float)((const double*)dense)[i];
-  f[(int64_t)k * g.plane + (int64_t)y * g.pitch + x] = v;
+  const double v = dtype == 0 ? (double)((const float*)dense)[i] : ((const double*)dense)[i];
+  f[(int64_t)k * g.plane + (int64_t)y * g.pitch + x] = (float)(v - weight(k));
 }
 
 __global__ void fill_int_kernel(int* p, int value) { *p = value; }
 
 constexpr Variant kVariants[] = {
-    {"tx256_ty1_xcd_nt", 256, 1, 1, 1},
-    {"tx256_ty1_nt", 256, 1, 0, 1},
-    {"tx256_ty1_xcd", 256, 1, 1, 0},
-    {"tx256_ty2_xcd_nt", 256, 2, 1, 1},
-    {"tx256_ty4_xcd_nt", 256, 4, 1, 1},
+    // name              tile_x tile_y vx remap nt
+    {"v1_ty1_nt", 256, 1, 1, 0, 1},
+    {"v1_ty1_xcd_nt", 256, 1, 1, 1, 1},
+    {"v1_ty1", 256, 1, 1, 0, 0},
+    {"v1_ty2_nt", 256, 2, 1, 0, 1},
+    {"v2_ty1_nt", 512, 1, 2, 0, 1},
+    {"v4_ty1_nt", 1024, 1, 4, 0, 1},
+    {"v4_ty1_xcd_nt", 1024, 1, 4, 1, 1},
 };
 
 }  // namespace
@@ -409,25 +500,27 @@ const Variant& variant(int v) { return kVariants[v - 1]; }
 
 hipError_t launch_step(const StepArgs& a, int v, hipStream_t s) {
   const Variant& var = variant(v);
-  const dim3 grid((unsigned)(a.t.ntx * a.t.nty)), block((unsigned)var.tile_x);
-  if (var.tile_y == 1) {
-    if (var.nontemporal)
-      hipLaunchKernelGGL((step_kernel<1, true>), grid, block, 0, s, a);
-    else
-      hipLaunchKernelGGL((step_kernel<1, false>), grid, block, 0, s, a);
-  } else if (var.tile_y == 2) {
-    hipLaunchKernelGGL((step_kernel<2, true>), grid, block, 0, s, a);
-  } else {
-    hipLaunchKernelGGL((step_kernel<4, true>), grid, block, 0, s, a);
+  const dim3 grid((unsigned)(a.t.ntx * a.t.nty)), block(256);
+#define LBM_CASE(TY, VX, NT)                                                       \
+  if (var.tile_y == TY && var.vx == VX && var.nontemporal == NT) {                  \
+    hipLaunchKernelGGL((step_kernel<TY, VX, NT>), grid, block, 0, s, a);            \
+    return hipGetLastError();                                                       \
   }
-  return hipGetLastError();
+  LBM_CASE(1, 1, 1)
+  LBM_CASE(1, 1, 0)
+  LBM_CASE(2, 1, 1)
+  LBM_CASE(1, 2, 1)
+  LBM_CASE(1, 4, 1)
+#undef LBM_CASE
+  return hipErrorInvalidValue;
 }
 
-hipError_t launch_force_reduce(const double2* partials, int nslots, int count, double* hist,
+hipError_t launch_force_reduce(const double2* partials, int nnodes, int count, double* hist,
                                int64_t cap, int64_t* dev_step, int* bad, int64_t* bad_step,
                                hipStream_t s) {
-  hipLaunchKernelGGL(force_reduce_kernel, dim3(1), dim3(256), 0, s, partials, nslots, count, hist,
-                     cap, dev_step, bad, bad_step);
+  hipLaunchKernelGGL(force_reduce_kernel, dim3(count), dim3(256), 0, s, partials, nnodes, hist, cap,
+                     (const int64_t*)dev_step);
+  hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(1), 0, s, count, dev_step, bad, bad_step);
   return hipGetLastError();
 }
 

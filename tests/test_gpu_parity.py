@@ -173,17 +173,18 @@ def test_variants_and_repeats_are_bitwise_identical(kw):
 
 
 def test_checkpoint_round_trip_is_bitwise():
+    """A float64 checkpoint holds the stored FP32 deviations exactly."""
     kw = dict(WORKLOADS["cyl_d10"])
     a = lbm.Lattice(lbm.make_params(**kw))
     a.step(150)
-    mid = a.get_populations()
+    mid = a.get_populations(np.float64)
     a.step(70)
-    end = a.get_populations()
+    end = a.get_populations(np.float64)
     fa = a.forces(151, 70)
     b = lbm.Lattice(lbm.make_params(**kw))
     b.set_populations(mid)
     b.step(70)
-    assert np.array_equal(b.get_populations(), end)
+    assert np.array_equal(b.get_populations(np.float64), end)
     assert np.array_equal(b.forces(1, 70)[0], fa[0])
 
 
