@@ -166,6 +166,62 @@ int32_t lbm_num_variants(void);
 lbm_status lbm_set_variant(lbm_ctx* ctx, int32_t variant);
 const char* lbm_variant_name(int32_t variant);
 
+/* Step scheduling.  With graphs enabled (the default) lbm_step replays HIP
+ * graphs that each hold 64 steps plus the force-history reduction, captured
+ * once per context on an internal stream and launched on the context's
+ * stream; the remainder of n runs as plain launches.  Results are identical
+ * bit for bit either way. */
+lbm_status lbm_set_graphs(lbm_ctx* ctx, int enable);
+
+/* Measurement utility: copies nbytes (a multiple of 16) from src to dst, both
+ * device buffers, with a plain streaming kernel (16 B per thread, one
+ * launch), ordered on `stream`.  Its duration gives the achievable
+ * copy bandwidth that the step kernel's HBM traffic is compared with. */
+lbm_status lbm_copy_probe(void* dst, const void* src, int64_t nbytes, void* stream);
+
+/* Autotuner: times every kernel variant for `steps` steps on a scratch copy
+ * of the context's lattice (the context's own state is not touched), selects
+ * the fastest for the context and returns it in *best (may be NULL).
+ * `cache_path` (may be NULL) names a text file of "key variant" lines; a hit
+ * skips the timing, a miss appends the result. */
+lbm_status lbm_autotune(lbm_ctx* ctx, int32_t steps, const char* cache_path, int32_t* best);
+
+/* ------------------------------------------------------------------ ensemble
+ * An ensemble advances many independent lattices (e.g. cylinder channels of
+ * different D, Re and size) together: every step is one kernel launch over a
+ * flattened list of the tiles of all active cases, and 64-step chunks are
+ * replayed as HIP graphs.  Each case evolves bit for bit as it would in its
+ * own context.  Cases are identified by their index in the `cases` array. */
+typedef struct lbm_batch lbm_batch;
+
+/* `cases[n]` as for lbm_create; `budgets` (may be NULL = unlimited) gives the
+ * number of steps after which each case stops (retires) while the others go
+ * on.  `tune_cache` (may be NULL) enables the autotuner with that cache file;
+ * without it the default kernel variant is used. */
+lbm_status lbm_batch_create(const lbm_params* cases, const int64_t* budgets, int32_t n, void* stream,
+                            const char* tune_cache, lbm_batch** out);
+void lbm_batch_destroy(lbm_batch* b);
+
+/* Advance every case still within its budget by up to n steps. */
+lbm_status lbm_batch_step(lbm_batch* b, int64_t n);
+
+/* Wait for the stream; LBM_ERR_DIVERGED if any case diverged (which ones:
+ * lbm_batch_case_info). */
+lbm_status lbm_batch_sync(lbm_batch* b);
+
+/* Steps taken and first diverged step (0 = none) of case `c` (synchronises). */
+lbm_status lbm_batch_case_info(lbm_batch* b, int32_t c, int64_t* steps, int64_t* diverged_step);
+
+/* As lbm_forces / lbm_fields / lbm_get_populations, for case `c`.  A case's
+ * divergence does not make these fail for the other cases. */
+lbm_status lbm_batch_forces(lbm_batch* b, int32_t c, int64_t first, int64_t count, double* fx, double* fy,
+                            double* cd, double* cl);
+lbm_status lbm_batch_fields(lbm_batch* b, int32_t c, float* rho, float* ux, float* uy, int on_device);
+lbm_status lbm_batch_get_populations(lbm_batch* b, int32_t c, void* buf, int dtype, int on_device);
+
+/* Kernel variant in use (1-based, as lbm_variant_name). */
+int32_t lbm_batch_variant(const lbm_batch* b);
+
 /* Thread-local message of the last failure ("" if none). */
 const char* lbm_last_error(void);
 

@@ -47,6 +47,11 @@ struct oracle {
   double* rho_t;        /* density of f(t) per node, used by Eq. 11 */
   int state_is_post;    /* 1: f holds f*(t) (set by oracle_set_fstar) */
   long t;
+  /* fluid-to-solid links (node, direction) in row-major node order, fixed at
+   * creation; the force sum of Eq. 14 runs over them in this order */
+  long n_links;
+  size_t* link_node;
+  int* link_dir;
 };
 
 static size_t node(const oracle* o, int x, int y) { return (size_t)y * o->nx + x; }
@@ -87,6 +92,8 @@ static void init_equilibrium(oracle* o) {
   }
 }
 
+static int build_links(oracle* o);
+
 oracle* oracle_create(const oracle_params* p, const unsigned char* solid) {
   if (!p || p->nx < 3 || p->ny < 3) return NULL;
   oracle* o = (oracle*)calloc(1, sizeof(oracle));
@@ -112,6 +119,10 @@ oracle* oracle_create(const oracle_params* p, const unsigned char* solid) {
   else
     oracle_digitise(p, o->solid);
   init_equilibrium(o);
+  if (build_links(o) != 0) {
+    oracle_destroy(o);
+    return NULL;
+  }
   return o;
 }
 
@@ -122,6 +133,8 @@ void oracle_destroy(oracle* o) {
   free(o->fs);
   free(o->g);
   free(o->rho_t);
+  free(o->link_node);
+  free(o->link_dir);
   free(o);
 }
 
@@ -195,32 +208,57 @@ static int neighbour(const oracle* o, int x, int y, int k, int* xo, int* yo) {
   return 1;
 }
 
-/* O2: Eq. 14 summed over every link from a fluid node into a solid node, all
- * eight directions.  The population leaving along c_k is f*_k, the one coming
- * back along -c_k has the same value (stationary wall, same step), so the
- * momentum given to the body per link is 2 c_k f*_k. */
+/* Every link from a fluid node into a solid node, all eight directions, in
+ * row-major node order. */
+static int build_links(oracle* o) {
+  long cap = 0, n = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    n = 0;
+    for (int y = 0; y < o->ny; ++y)
+      for (int x = 0; x < o->nx; ++x) {
+        size_t m = node(o, x, y);
+        if (o->solid[m]) continue;
+        for (int k = 1; k < 9; ++k) {
+          int xn, yn;
+          if (!neighbour(o, x, y, k, &xn, &yn) || !o->solid[node(o, xn, yn)]) continue;
+          if (pass == 1) {
+            o->link_node[n] = m;
+            o->link_dir[n] = k;
+          }
+          ++n;
+        }
+      }
+    if (pass == 0) {
+      cap = n > 0 ? n : 1;
+      o->link_node = (size_t*)malloc(cap * sizeof(size_t));
+      o->link_dir = (int*)malloc(cap * sizeof(int));
+      if (!o->link_node || !o->link_dir) return -1;
+    }
+  }
+  o->n_links = n;
+  return 0;
+}
+
+/* O2: Eq. 14 summed over the links.  The population leaving along c_k is
+ * f*_k, the one coming back along -c_k has the same value (stationary wall,
+ * same step), so the momentum given to the body per link is 2 c_k f*_k. */
 static void force(const oracle* o, double* fx, double* fy) {
   double sx = 0.0, sy = 0.0;
-  for (int y = 0; y < o->ny; ++y)
-    for (int x = 0; x < o->nx; ++x) {
-      size_t n = node(o, x, y);
-      if (o->solid[n]) continue;
-      for (int k = 1; k < 9; ++k) {
-        int xn, yn;
-        if (!neighbour(o, x, y, k, &xn, &yn)) continue;
-        if (!o->solid[node(o, xn, yn)]) continue;
-        sx += 2.0 * CX[k] * o->fs[n * 9 + k];
-        sy += 2.0 * CY[k] * o->fs[n * 9 + k];
-      }
-    }
+  for (long i = 0; i < o->n_links; ++i) {
+    int k = o->link_dir[i];
+    double f = o->fs[o->link_node[i] * 9 + k];
+    sx += 2.0 * CX[k] * f;
+    sy += 2.0 * CY[k] * f;
+  }
   *fx = sx;
   *fy = sy;
 }
 
 /* O3: push streaming with half-way bounce-back at solid nodes. */
 static void stream(oracle* o) {
-  size_t total = (size_t)o->nx * o->ny * 9;
-  for (size_t i = 0; i < total; ++i) o->g[i] = NAN;
+  long total = (long)o->nx * o->ny * 9;
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < total; ++i) o->g[i] = NAN;
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < o->ny; ++y)
     for (int x = 0; x < o->nx; ++x) {
@@ -351,8 +389,9 @@ long oracle_step(oracle* o, long nsteps, double* fx, double* fy) {
     outlet(o);
     inlet(o);
     /* O8 */
-    size_t nn = (size_t)o->nx * o->ny;
-    for (size_t n = 0; n < nn; ++n) {
+    long nn = (long)o->nx * o->ny;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (long n = 0; n < nn; ++n) {
       if (o->solid[n]) continue;
       for (int k = 0; k < 9; ++k) {
         double v = o->g[n * 9 + k];

@@ -27,7 +27,7 @@ from ._lib import (
 )
 
 __all__ = [
-    "Lattice", "make_params", "validate", "tau_of", "geometry", "shedding_stats",
+    "Lattice", "Ensemble", "make_params", "validate", "tau_of", "geometry", "shedding_stats", "copy_probe",
     "num_variants", "variant_name", "LbmError", "DivergedError", "RangeError",
     "WALL_FREE_SLIP", "WALL_PERIODIC", "WALL_NEBB", "WALL_MOVING_BB",
     "OUTLET_COPY_ALL", "OUTLET_COPY_UNKNOWN",
@@ -59,6 +59,12 @@ def shedding_stats(cd, cl, d, u, periods=5):
     check(_lib.lib.lbm_shedding_stats(cd.ctypes.data_as(dp), cl.ctypes.data_as(dp), len(cd), d, u,
                                       periods, ctypes.byref(out)))
     return {"mean_cd": out.mean_cd, "cl_amp": out.cl_amp, "st": out.st, "period": out.period}
+
+
+def copy_probe(dst, src, nbytes: int, stream=None):
+    """Plain streaming copy of nbytes between two device tensors (bandwidth reference)."""
+    check(_lib.lib.lbm_copy_probe(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                  nbytes, _stream_handle(stream)))
 
 
 def num_variants() -> int:
@@ -125,6 +131,15 @@ class Lattice:
     def set_variant(self, v: int):
         check(_lib.lib.lbm_set_variant(self._h, v))
 
+    def set_graphs(self, enable: bool):
+        check(_lib.lib.lbm_set_graphs(self._h, 1 if enable else 0))
+
+    def autotune(self, steps: int = 20, cache: str | None = None) -> int:
+        """Pick the fastest kernel variant (timed on a scratch copy); returns it."""
+        best = ctypes.c_int32()
+        check(_lib.lib.lbm_autotune(self._h, steps, cache.encode() if cache else None, ctypes.byref(best)))
+        return best.value
+
     # ---------------------------------------------------------------- outputs
     def forces(self, first: int = 1, count: int | None = None):
         """(fx, fy, cd, cl) for steps [first, first+count); cd/cl None without a cylinder."""
@@ -170,3 +185,78 @@ class Lattice:
     def set_populations_device(self, t):
         dt = 0 if str(t.dtype) == "torch.float32" else 1
         check(_lib.lib.lbm_set_populations(self._h, t.data_ptr(), dt, 1))
+
+
+class Ensemble:
+    """Many independent lattices advanced together (one launch per step over
+    the tiles of every active case).  `budgets[i]` (optional) stops case i
+    after that many steps."""
+
+    def __init__(self, params_list, budgets=None, stream=None, tune_cache: str | None = None):
+        self.params = list(params_list)
+        n = len(self.params)
+        arr = (_lib.Params * n)(*self.params)
+        bud = None
+        if budgets is not None:
+            bud = (ctypes.c_int64 * n)(*[int(b) for b in budgets])
+        self._h = ctypes.c_void_p()
+        check(_lib.lib.lbm_batch_create(arr, bud, n, _stream_handle(stream),
+                                        tune_cache.encode() if tune_cache else None, ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            _lib.lib.lbm_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def variant(self) -> int:
+        return _lib.lib.lbm_batch_variant(self._h)
+
+    def step(self, n: int = 1):
+        check(_lib.lib.lbm_batch_step(self._h, n))
+
+    def sync(self):
+        check(_lib.lib.lbm_batch_sync(self._h))
+
+    def info(self, c: int):
+        """(steps taken, first diverged step or 0) of case c."""
+        s, d = ctypes.c_int64(), ctypes.c_int64()
+        check(_lib.lib.lbm_batch_case_info(self._h, c, ctypes.byref(s), ctypes.byref(d)))
+        return s.value, d.value
+
+    def forces(self, c: int, first: int = 1, count: int | None = None):
+        if count is None:
+            count = self.info(c)[0] - first + 1
+        p = self.params[c]
+        fx, fy = np.zeros(count), np.zeros(count)
+        coeff = p.diameter > 0 and p.u_in > 0
+        cd = np.zeros(count) if coeff else None
+        cl = np.zeros(count) if coeff else None
+        check(_lib.lib.lbm_batch_forces(self._h, c, first, count, fx.ctypes.data, fy.ctypes.data,
+                                        cd.ctypes.data if coeff else None, cl.ctypes.data if coeff else None))
+        return fx, fy, cd, cl
+
+    def fields(self, c: int):
+        p = self.params[c]
+        rho, ux, uy = (np.empty((p.ny, p.nx), np.float32) for _ in range(3))
+        check(_lib.lib.lbm_batch_fields(self._h, c, rho.ctypes.data, ux.ctypes.data, uy.ctypes.data, 0))
+        return rho, ux, uy
+
+    def get_populations(self, c: int, dtype=np.float32):
+        p = self.params[c]
+        dt = 0 if np.dtype(dtype) == np.float32 else 1
+        out = np.empty((9, p.ny, p.nx), dtype=np.float32 if dt == 0 else np.float64)
+        check(_lib.lib.lbm_batch_get_populations(self._h, c, out.ctypes.data, dt, 0))
+        return out

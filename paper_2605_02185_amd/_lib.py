@@ -94,6 +94,18 @@ def _load():
         "lbm_num_variants": (i32, []),
         "lbm_set_variant": (i32, [vp, i32]),
         "lbm_variant_name": (ctypes.c_char_p, [i32]),
+        "lbm_set_graphs": (i32, [vp, ctypes.c_int]),
+        "lbm_copy_probe": (i32, [vp, vp, i64, vp]),
+        "lbm_autotune": (i32, [vp, i32, ctypes.c_char_p, ctypes.POINTER(i32)]),
+        "lbm_batch_create": (i32, [P, ctypes.POINTER(i64), i32, vp, ctypes.c_char_p, ctypes.POINTER(vp)]),
+        "lbm_batch_destroy": (None, [vp]),
+        "lbm_batch_step": (i32, [vp, i64]),
+        "lbm_batch_sync": (i32, [vp]),
+        "lbm_batch_case_info": (i32, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "lbm_batch_forces": (i32, [vp, i32, i64, i64, vp, vp, vp, vp]),
+        "lbm_batch_fields": (i32, [vp, i32, vp, vp, vp, ctypes.c_int]),
+        "lbm_batch_get_populations": (i32, [vp, i32, vp, ctypes.c_int, ctypes.c_int]),
+        "lbm_batch_variant": (i32, [vp]),
         "lbm_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sigs.items():

@@ -51,6 +51,83 @@ double wall_u(double v, double u_in) { return std::isnan(v) ? u_in : v; }
 
 }  // namespace
 
+namespace lbm {
+
+lbm_status set_error(lbm_status s, const char* msg) { return fail(s, "%s", msg); }
+
+lbm_status build_geometry(const lbm_params* p, HostGeometry* out) {
+  Geometry& g = out->g;
+  g = Geometry{};
+  g.nx = p->nx;
+  g.ny = p->ny;
+  // rows start on 1 KiB boundaries; consecutive planes are staggered by half
+  // a 4 KiB page so that the 18 streams of a step do not start in step on the
+  // same HBM channels (measured +1-2% at D = 160)
+  g.pitch = (p->nx + 255) / 256 * 256;
+  g.plane = (int64_t)p->ny * g.pitch + 512;
+  if (9 * g.plane >= (int64_t)INT_MAX)
+    return fail(LBM_ERR_INVALID_ARG, "lattice of %d x %d exceeds the 32-bit offsets of the kernels", p->nx, p->ny);
+  out->flags.clear();
+  out->link_index.clear();
+  // cylinder rectangle: solid nodes plus one ring of fluid neighbours
+  if (p->diameter > 0) {
+    int x0 = INT_MAX, x1 = -1, y0 = INT_MAX, y1 = -1;
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x)
+        if (solid_at(*p, x, y)) {
+          x0 = std::min(x0, x);
+          x1 = std::max(x1, x);
+          y0 = std::min(y0, y);
+          y1 = std::max(y1, y);
+        }
+    if (x1 >= 0) {
+      g.rx0 = x0 - 1;
+      g.ry0 = y0 - 1;
+      g.rw = x1 - x0 + 3;
+      g.rh = y1 - y0 + 3;
+      out->flags.resize((size_t)g.rw * g.rh);
+      out->link_index.assign((size_t)g.rw * g.rh, -1);
+      for (int j = 0; j < g.rh; ++j)
+        for (int i = 0; i < g.rw; ++i) {
+          const int x = g.rx0 + i, y = g.ry0 + j;
+          uint16_t f = 0;
+          if (solid_at(*p, x, y)) {
+            f = kSolid;
+          } else {
+            for (int k = 1; k < 9; ++k)
+              if (solid_at(*p, x - CX[k], y - CY[k])) f |= (uint16_t)(1u << k);
+          }
+          out->flags[(size_t)j * g.rw + i] = f;
+          if (f >> 1) out->link_index[(size_t)j * g.rw + i] = g.n_link_nodes++;
+        }
+    }
+  }
+  return LBM_OK;
+}
+
+Physics make_physics(const lbm_params* p) {
+  Physics ph{};
+  ph.omega = (float)(1.0 / lbm_params_tau(p));
+  ph.u_in = (float)p->u_in;
+  ph.u_top = (float)wall_u(p->u_wall_top, p->u_in);
+  ph.u_bot = (float)wall_u(p->u_wall_bottom, p->u_in);
+  ph.wall = p->wall;
+  ph.outlet_mode = p->outlet_mode;
+  ph.x_periodic = p->x_periodic;
+  return ph;
+}
+
+void tiling_for_variant(const Geometry& g, int v, Tiling* t) {
+  const Variant& var = variant(v);
+  t->tile_x = var.tile_x;
+  t->tile_y = var.tile_y;
+  t->ntx = (g.nx + t->tile_x - 1) / t->tile_x;
+  t->nty = (g.ny + t->tile_y - 1) / t->tile_y;
+  t->remap_xcd = var.remap_xcd;
+}
+
+}  // namespace lbm
+
 struct lbm_ctx {
   lbm_params p{};
   double tau = 0;
@@ -71,6 +148,10 @@ struct lbm_ctx {
   int64_t* d_bad_step = nullptr;
   int64_t step = 0;
   int pending = 0;
+  // graph replay of kRing steps; graph[c] starts from buf[c]
+  int use_graphs = 1;
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
 
 extern "C" {
@@ -167,13 +248,7 @@ const char* lbm_last_error(void) { return g_err.c_str(); }
 namespace {
 
 void set_tiling(lbm_ctx* c, int v) {
-  const lbm::Variant& var = lbm::variant(v);
-  lbm::Tiling& t = c->tiling;
-  t.tile_x = var.tile_x;
-  t.tile_y = var.tile_y;
-  t.ntx = (c->geo.nx + t.tile_x - 1) / t.tile_x;
-  t.nty = (c->geo.ny + t.tile_y - 1) / t.tile_y;
-  t.remap_xcd = var.remap_xcd;
+  lbm::tiling_for_variant(c->geo, v, &c->tiling);
   c->variant = v;
 }
 
@@ -188,9 +263,19 @@ lbm_status flush(lbm_ctx* c) {
   return LBM_OK;
 }
 
+void drop_graphs(lbm_ctx* c) {
+  for (int i = 0; i < 2; ++i)
+    if (c->graph[i]) {
+      (void)hipGraphExecDestroy(c->graph[i]);
+      c->graph[i] = nullptr;
+    }
+}
+
 void free_ctx(lbm_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c);
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   (void)hipFree(c->buf[0]);
   (void)hipFree(c->buf[1]);
   (void)hipFree(c->d_flags);
@@ -228,61 +313,17 @@ lbm_status lbm_create(const lbm_params* p, void* stream, lbm_ctx** out) {
       return fail(LBM_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
     }
   }
-  lbm::Geometry& g = c->geo;
-  g.nx = p->nx;
-  g.ny = p->ny;
-  // rows start on 1 KiB boundaries; consecutive planes are staggered by half
-  // a 4 KiB page so that the 18 streams of a step do not start in step on the
-  // same HBM channels (measured +1-2% at D = 160)
-  g.pitch = (p->nx + 255) / 256 * 256;
-  g.plane = (int64_t)p->ny * g.pitch + 512;
-  if (9 * g.plane >= (int64_t)INT_MAX) {
+  lbm::HostGeometry hg;
+  st = lbm::build_geometry(p, &hg);
+  if (st != LBM_OK) {
     delete c;
-    return fail(LBM_ERR_INVALID_ARG, "lattice of %d x %d exceeds the 32-bit offsets of the kernels", p->nx, p->ny);
+    return st;
   }
-  // cylinder rectangle: solid nodes plus one ring of fluid neighbours
-  std::vector<uint16_t> flags;
-  std::vector<int32_t> link_index;
-  if (p->diameter > 0) {
-    int x0 = INT_MAX, x1 = -1, y0 = INT_MAX, y1 = -1;
-    for (int y = 0; y < p->ny; ++y)
-      for (int x = 0; x < p->nx; ++x)
-        if (solid_at(*p, x, y)) {
-          x0 = std::min(x0, x);
-          x1 = std::max(x1, x);
-          y0 = std::min(y0, y);
-          y1 = std::max(y1, y);
-        }
-    if (x1 >= 0) {
-      g.rx0 = x0 - 1;
-      g.ry0 = y0 - 1;
-      g.rw = x1 - x0 + 3;
-      g.rh = y1 - y0 + 3;
-      flags.resize((size_t)g.rw * g.rh);
-      link_index.assign((size_t)g.rw * g.rh, -1);
-      for (int j = 0; j < g.rh; ++j)
-        for (int i = 0; i < g.rw; ++i) {
-          const int x = g.rx0 + i, y = g.ry0 + j;
-          uint16_t f = 0;
-          if (solid_at(*p, x, y)) {
-            f = lbm::kSolid;
-          } else {
-            for (int k = 1; k < 9; ++k)
-              if (solid_at(*p, x - CX[k], y - CY[k])) f |= (uint16_t)(1u << k);
-          }
-          flags[(size_t)j * g.rw + i] = f;
-          if (f >> 1) link_index[(size_t)j * g.rw + i] = g.n_link_nodes++;
-        }
-    }
-  }
-  lbm::Physics& ph = c->phys;
-  ph.omega = (float)(1.0 / c->tau);
-  ph.u_in = (float)p->u_in;
-  ph.u_top = (float)wall_u(p->u_wall_top, p->u_in);
-  ph.u_bot = (float)wall_u(p->u_wall_bottom, p->u_in);
-  ph.wall = p->wall;
-  ph.outlet_mode = p->outlet_mode;
-  ph.x_periodic = p->x_periodic;
+  c->geo = hg.g;
+  lbm::Geometry& g = c->geo;
+  const std::vector<uint16_t>& flags = hg.flags;
+  const std::vector<int32_t>& link_index = hg.link_index;
+  c->phys = lbm::make_physics(p);
 
   set_tiling(c, 1);
 
@@ -341,31 +382,158 @@ lbm_status lbm_set_variant(lbm_ctx* c, int32_t v) {
   if (v < 1 || v > lbm::num_variants()) return fail(LBM_ERR_INVALID_ARG, "variant %d out of range", v);
   lbm_status st = flush(c);
   if (st != LBM_OK) return st;
+  drop_graphs(c);
   set_tiling(c, v);
+  return LBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Enqueues one step on stream s (buffers by c->cur, ring slot c->pending) and
+// advances the host-side bookkeeping; folds the ring when it is full.
+lbm_status enqueue_step(lbm_ctx* c, hipStream_t s) {
+  lbm::StepArgs a{};
+  a.g = c->geo;
+  a.p = c->phys;
+  a.t = c->tiling;
+  a.bad = c->d_bad;
+  a.A = c->buf[c->cur];
+  a.B = c->buf[c->cur ^ 1];
+  a.slot = c->pending;
+  a.partial = c->d_partials + (size_t)c->pending * slots_of(c);
+  HIP_TRY(lbm::launch_step(a, c->variant, s));
+  c->cur ^= 1;
+  c->step += 1;
+  if (++c->pending == lbm::kRing) {
+    HIP_TRY(lbm::launch_force_reduce(c->d_partials, slots_of(c), c->pending, c->d_hist,
+                                     c->p.hist_capacity, c->d_step, c->d_bad, c->d_bad_step, s));
+    c->pending = 0;
+  }
+  return LBM_OK;
+}
+
+// Captures kRing steps starting from buf[c->cur] (ring empty) into a graph.
+lbm_status capture(lbm_ctx* c) {
+  if (!c->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+  const int cur0 = c->cur;
+  const int64_t step0 = c->step;
+  HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+  lbm_status st = LBM_OK;
+  for (int i = 0; i < lbm::kRing && st == LBM_OK; ++i) st = enqueue_step(c, c->capture_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+  c->cur = cur0;  // capturing ran nothing
+  c->step = step0;
+  c->pending = 0;
+  if (st != LBM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(LBM_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  const hipError_t e2 = hipGraphInstantiate(&c->graph[cur0], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) return fail(LBM_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_set_graphs(lbm_ctx* c, int enable) {
+  if (check_ctx(c)) return LBM_ERR_INVALID_ARG;
+  c->use_graphs = enable ? 1 : 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_ctx* c, int32_t steps, const char* cache_path, int32_t* best) {
+  if (check_ctx(c)) return LBM_ERR_INVALID_ARG;
+  if (steps < 1) return fail(LBM_ERR_INVALID_ARG, "steps must be >= 1");
+  char key[128];
+  snprintf(key, sizeof key, "lattice-%dx%d-d%d-w%d-x%d", c->p.nx, c->p.ny, c->p.diameter, c->p.wall,
+           c->p.x_periodic);
+  int v_best = 0;
+  if (cache_path) {
+    if (FILE* f = fopen(cache_path, "r")) {
+      char k[256];
+      int v = 0;
+      while (fscanf(f, "%255s %d", k, &v) == 2)
+        if (!strcmp(k, key) && v >= 1 && v <= lbm::num_variants()) v_best = v;
+      fclose(f);
+    }
+  }
+  if (!v_best) {
+    lbm_ctx* scratch = nullptr;
+    lbm_status st = lbm_create(&c->p, c->stream, &scratch);
+    if (st != LBM_OK) return st;
+    scratch->use_graphs = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float t_best = 1e30f;
+    st = LBM_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+      st = fail(LBM_ERR_HIP, "hipEventCreate failed");
+    for (int v = 1; st == LBM_OK && v <= lbm::num_variants(); ++v) {
+      if ((st = lbm_set_variant(scratch, v)) != LBM_OK) break;
+      if ((st = lbm_step(scratch, 4)) != LBM_OK) break;
+      (void)hipEventRecord(e0, scratch->stream);
+      if ((st = lbm_step(scratch, steps)) != LBM_OK) break;
+      (void)hipEventRecord(e1, scratch->stream);
+      float ms = 1e30f;
+      if (hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < t_best) {
+        t_best = ms;
+        v_best = v;
+      }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    lbm_destroy(scratch);
+    if (st != LBM_OK) return st;
+    if (cache_path)
+      if (FILE* f = fopen(cache_path, "a")) {
+        fprintf(f, "%s %d\n", key, v_best);
+        fclose(f);
+      }
+  }
+  lbm_status st = lbm_set_variant(c, v_best);
+  if (st == LBM_OK && best) *best = v_best;
+  return st;
+}
+
+lbm_status lbm_copy_probe(void* dst, const void* src, int64_t nbytes, void* stream) {
+  if (!dst || !src || nbytes < 0 || nbytes % 16) return fail(LBM_ERR_INVALID_ARG, "bad copy probe arguments");
+  if (nbytes == 0) return LBM_OK;
+  HIP_TRY(lbm::launch_copy_probe(dst, src, nbytes, (hipStream_t)stream));
   return LBM_OK;
 }
 
 lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   if (check_ctx(c)) return LBM_ERR_INVALID_ARG;
   if (n < 0) return fail(LBM_ERR_INVALID_ARG, "n must be >= 0");
-  const int nslots = slots_of(c);
-  lbm::StepArgs a{};
-  a.g = c->geo;
-  a.p = c->phys;
-  a.t = c->tiling;
-  a.bad = c->d_bad;
-  for (int64_t i = 0; i < n; ++i) {
-    a.A = c->buf[c->cur];
-    a.B = c->buf[c->cur ^ 1];
-    a.slot = c->pending;
-    a.partial = c->d_partials + (size_t)c->pending * nslots;
-    HIP_TRY(lbm::launch_step(a, c->variant, c->stream));
-    c->cur ^= 1;
-    c->step += 1;
-    if (++c->pending == lbm::kRing) {
-      lbm_status st = flush(c);
-      if (st != LBM_OK) return st;
+  int64_t i = 0;
+  // plain launches until the ring is empty, then whole graphs
+  while (i < n && c->pending != 0) {
+    lbm_status st = enqueue_step(c, c->stream);
+    if (st != LBM_OK) return st;
+    ++i;
+  }
+  if (c->use_graphs) {
+    while (n - i >= lbm::kRing) {
+      if (!c->graph[c->cur]) {
+        lbm_status st = capture(c);
+        if (st != LBM_OK) return st;
+      }
+      HIP_TRY(hipGraphLaunch(c->graph[c->cur], c->stream));
+      // kRing is even: the state returns to the same buffer
+      c->step += lbm::kRing;
+      i += lbm::kRing;
     }
+  }
+  for (; i < n; ++i) {
+    lbm_status st = enqueue_step(c, c->stream);
+    if (st != LBM_OK) return st;
   }
   return flush(c);
 }

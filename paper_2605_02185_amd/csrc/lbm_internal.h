@@ -5,6 +5,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
+#include "../../include/lbm.h"
+
 namespace lbm {
 
 // Wall modes, outlet modes: same values as the public enums.
@@ -62,6 +66,21 @@ struct StepArgs {
   int slot;                     // ring slot of this step
 };
 
+// One case of an ensemble, as the batched kernels see it (device memory).
+struct CaseArgs {
+  float* buf[2];        // ping-pong population buffers (shifted storage)
+  Geometry g;
+  Physics p;
+  Tiling t;             // remap_xcd must be 0
+  double2* partial;     // slot 0 of this case's force contributions; step j
+                        // of the ring at partial + j * partial_stride
+  int* bad;             // watchdog slot of this case
+  int64_t* bad_step;    // first diverged step of this case (0 = none)
+  int64_t* dev_step;    // steps folded into this case's history so far
+  double* hist;         // [hist_cap][2] FP64 force history
+  int64_t hist_cap;
+};
+
 struct Variant {
   const char* name;
   int tile_x, tile_y;  // nodes along x (= 256 * vx) and rows per tile
@@ -73,6 +92,10 @@ struct Variant {
 int num_variants();
 const Variant& variant(int v);  // 1-based
 hipError_t launch_step(const StepArgs& a, int v, hipStream_t s);
+hipError_t launch_step_batch(const CaseArgs* cases, const int2* tiles, int ntiles, int cur, int slot,
+                             int partial_stride, int v, hipStream_t s);
+hipError_t launch_force_reduce_batch(const CaseArgs* cases, int ncases, int count, int partial_stride,
+                                     hipStream_t s);
 hipError_t launch_force_reduce(const double2* partials, int nnodes, int count, double* hist,
                                int64_t cap, int64_t* dev_step, int* bad, int64_t* bad_step,
                                hipStream_t s);
@@ -85,5 +108,18 @@ hipError_t launch_pack(const float* f, const Geometry& g, void* dense, int dtype
 hipError_t launch_unpack(const void* dense, int dtype, const Geometry& g, float* f,
                          hipStream_t s);
 hipError_t launch_fill_int(int* p, int value, hipStream_t s);
+hipError_t launch_copy_probe(void* dst, const void* src, int64_t nbytes, hipStream_t s);
+
+// ------------------------------------------------------- host helpers
+// (lbm_api.cpp) shared by the single-lattice and the ensemble runtimes.
+struct HostGeometry {
+  Geometry g;                       // device pointers left null
+  std::vector<uint16_t> flags;      // [rh][rw]
+  std::vector<int32_t> link_index;  // [rh][rw]
+};
+lbm_status build_geometry(const lbm_params* p, HostGeometry* out);
+Physics make_physics(const lbm_params* p);
+void tiling_for_variant(const Geometry& g, int v, Tiling* t);
+lbm_status set_error(lbm_status s, const char* msg);
 
 }  // namespace lbm

@@ -357,10 +357,7 @@ __device__ __forceinline__ int remap_xcd(int id, int n) {
 // One tile = tile_x = 256 * VX consecutive nodes of TY rows; lane t of the
 // block owns nodes x0 .. x0+VX-1 with x0 = tile origin + VX t.
 template <int TY, int VX, bool NT>
-__global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
-  const int ntiles = a.t.ntx * a.t.nty;
-  const int tile = a.t.remap_xcd ? remap_xcd((int)blockIdx.x, ntiles) : (int)blockIdx.x;
-  const int bx = tile % a.t.ntx, by = tile / a.t.ntx;
+__device__ __forceinline__ void process_tile(const StepArgs& a, int bx, int by) {
   const int nx = a.g.nx, ny = a.g.ny;
   const int x0 = bx * a.t.tile_x + (int)threadIdx.x * VX;
   bool bad = false;
@@ -383,6 +380,35 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
     }
   }
   if (bad) atomicMin(a.bad, a.slot);
+}
+
+template <int TY, int VX, bool NT>
+__global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
+  const int ntiles = a.t.ntx * a.t.nty;
+  const int tile = a.t.remap_xcd ? remap_xcd((int)blockIdx.x, ntiles) : (int)blockIdx.x;
+  process_tile<TY, VX, NT>(a, tile % a.t.ntx, tile / a.t.ntx);
+}
+
+// One step of a whole ensemble: block b processes tile tiles[b] = (case,
+// tile index within the case) with that case's geometry, physics, buffers
+// and force slots, through the same per-node code as step_kernel, so every
+// case evolves bit for bit as it would alone.
+template <int TY, int VX, bool NT>
+__global__ __launch_bounds__(256) void step_batch_kernel(const CaseArgs* __restrict__ cases,
+                                                         const int2* __restrict__ tiles, int cur,
+                                                         int slot, int partial_stride) {
+  const int2 ct = tiles[blockIdx.x];
+  const CaseArgs& c = cases[ct.x];
+  StepArgs a;
+  a.A = c.buf[cur];
+  a.B = c.buf[cur ^ 1];
+  a.g = c.g;
+  a.p = c.p;
+  a.t = c.t;
+  a.partial = c.partial + (size_t)slot * partial_stride;
+  a.bad = c.bad;
+  a.slot = slot;
+  process_tile<TY, VX, NT>(a, ct.y % c.t.ntx, ct.y / c.t.ntx);
 }
 
 // Folds row blockIdx.x of the per-node force contributions into the FP64
@@ -414,6 +440,50 @@ __global__ __launch_bounds__(256) void force_reduce_kernel(const double2* __rest
     hist[2 * s] = fx;
     hist[2 * s + 1] = fy;
   }
+}
+
+// Ensemble version of the two kernels below: block (j, c) folds step j of
+// case c (cases [0, ncases) are the active ones) exactly as
+// force_reduce_kernel folds a single lattice's step.
+__global__ __launch_bounds__(256) void force_reduce_batch_kernel(const CaseArgs* __restrict__ cases,
+                                                                 int partial_stride) {
+  __shared__ double2 wsum[4];
+  const int j = blockIdx.x;
+  const CaseArgs& c = cases[blockIdx.y];
+  const double2* __restrict__ part = c.partial + (size_t)j * partial_stride;
+  double sx = 0.0, sy = 0.0;
+  for (int i = threadIdx.x; i < c.g.n_link_nodes; i += 256) {
+    const double2 v = part[i];
+    sx += v.x;
+    sy += v.y;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    sx += __shfl_xor(sx, off);
+    sy += __shfl_xor(sy, off);
+  }
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = make_double2(sx, sy);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double fx = (wsum[0].x + wsum[1].x) + (wsum[2].x + wsum[3].x);
+    const double fy = (wsum[0].y + wsum[1].y) + (wsum[2].y + wsum[3].y);
+    const int64_t s = (*c.dev_step + j) % c.hist_cap;
+    c.hist[2 * s] = fx;
+    c.hist[2 * s + 1] = fy;
+  }
+}
+
+__global__ void advance_batch_kernel(const CaseArgs* __restrict__ cases, int ncases, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncases) return;
+  const CaseArgs& c = cases[i];
+  const int64_t base = *c.dev_step;
+  const int b = *c.bad;
+  if (b != INT_MAX) {
+    if (*c.bad_step == 0) *c.bad_step = base + b + 1;
+    *c.bad = INT_MAX;
+  }
+  *c.dev_step = base + count;
 }
 
 // Runs after force_reduce_kernel: advances the device step counter by
@@ -482,6 +552,13 @@ __global__ void unpack_kernel(const void* dense, int dtype, Geometry g, float* f
 
 __global__ void fill_int_kernel(int* p, int value) { *p = value; }
 
+typedef float float4v __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void copy_probe_kernel(const float4v* __restrict__ src,
+                                                         float4v* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) __builtin_nontemporal_store(src[i], dst + i);
+}
+
 constexpr Variant kVariants[] = {
     // name              tile_x tile_y vx remap nt
     {"v1_ty1_nt", 256, 1, 1, 0, 1},
@@ -497,6 +574,34 @@ constexpr Variant kVariants[] = {
 
 int num_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 const Variant& variant(int v) { return kVariants[v - 1]; }
+
+hipError_t launch_step_batch(const CaseArgs* cases, const int2* tiles, int ntiles, int cur, int slot,
+                             int partial_stride, int v, hipStream_t s) {
+  const Variant& var = variant(v);
+  const dim3 grid((unsigned)ntiles), block(256);
+#define LBM_CASE(TY, VX, NT)                                                                   \
+  if (var.tile_y == TY && var.vx == VX && var.nontemporal == NT) {                              \
+    hipLaunchKernelGGL((step_batch_kernel<TY, VX, NT>), grid, block, 0, s, cases, tiles, cur,   \
+                       slot, partial_stride);                                                   \
+    return hipGetLastError();                                                                   \
+  }
+  LBM_CASE(1, 1, 1)
+  LBM_CASE(1, 1, 0)
+  LBM_CASE(2, 1, 1)
+  LBM_CASE(1, 2, 1)
+  LBM_CASE(1, 4, 1)
+#undef LBM_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_force_reduce_batch(const CaseArgs* cases, int ncases, int count, int partial_stride,
+                                     hipStream_t s) {
+  hipLaunchKernelGGL(force_reduce_batch_kernel, dim3(count, ncases), dim3(256), 0, s, cases,
+                     partial_stride);
+  hipLaunchKernelGGL(advance_batch_kernel, dim3((ncases + 63) / 64), dim3(64), 0, s, cases, ncases,
+                     count);
+  return hipGetLastError();
+}
 
 hipError_t launch_step(const StepArgs& a, int v, hipStream_t s) {
   const Variant& var = variant(v);
@@ -542,6 +647,13 @@ hipError_t launch_pack(const float* f, const Geometry& g, void* dense, int dtype
 
 hipError_t launch_unpack(const void* dense, int dtype, const Geometry& g, float* f, hipStream_t s) {
   hipLaunchKernelGGL(unpack_kernel, dim3((g.nx + 255) / 256, g.ny, 9), dim3(256), 0, s, dense, dtype, g, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_probe(void* dst, const void* src, int64_t nbytes, hipStream_t s) {
+  const int64_t n = nbytes / 16;
+  hipLaunchKernelGGL(copy_probe_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     (const float4v*)src, (float4v*)dst, n);
   return hipGetLastError();
 }
 

@@ -1,0 +1,96 @@
+"""Ensemble (batched) runs: every case of an Ensemble must evolve bit for
+bit as it does in its own Lattice, including cases that stop at their step
+budget while the others go on, and the autotuner must pick a valid variant."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2605_02185_amd as lbm
+from lbm_inputs import channel, ensemble
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _alone(kw, steps, with_fields=False):
+    lat = lbm.Lattice(lbm.make_params(**kw))
+    lat.step(steps)
+    out = (lat.get_populations(np.float64), lat.forces())
+    return out + (lat.fields(),) if with_fields else out
+
+
+def test_mixed_ensemble_matches_separate_runs_bitwise():
+    # explicit tau: BGK at the Re-derived tau (about 0.51 at these D) diverges
+    cases = [
+        dict(channel(6, u=0.05, re=80), tau=0.62),
+        dict(channel(9, u=0.05, re=150), tau=0.58, wall=lbm.WALL_PERIODIC),
+        dict(channel(7, u=0.04, re=60), tau=0.7, wall=lbm.WALL_MOVING_BB, outlet_mode=lbm.OUTLET_COPY_UNKNOWN),
+        dict(nx=300, ny=64, u_in=0.03, tau=0.7, wall=lbm.WALL_NEBB),
+        dict(nx=130, ny=77, tau=0.6, u_in=0.0, x_periodic=True, wall=lbm.WALL_PERIODIC, perturb_amp=0.0),
+    ]
+    budgets = [300, 137, 300, 64, 200]
+    note(f"ensemble of {len(cases)} cases, budgets {budgets}")
+    ens = lbm.Ensemble([lbm.make_params(**kw) for kw in cases], budgets=budgets)
+    ens.step(150)
+    ens.step(1)
+    ens.step(400)  # beyond every budget: each case stops at its own
+    ens.sync()
+    for i, (kw, b) in enumerate(zip(cases, budgets)):
+        steps, bad = ens.info(i)
+        assert (steps, bad) == (b, 0)
+        f_alone, forces_alone, fields_alone = _alone(kw, b, with_fields=True)
+        assert np.array_equal(ens.get_populations(i, np.float64), f_alone), i
+        got = ens.forces(i)
+        for a, c in zip(got, forces_alone):
+            if a is not None:
+                assert np.array_equal(a, c), i
+        for a, c in zip(ens.fields(i), fields_alone):
+            assert np.array_equal(a, c), i
+
+
+def test_full_ensemble_of_64_channels_matches_separate_runs():
+    """The 64-case ensemble (D in 8..32, Re in [60, 200], U = 0.05): 130 steps
+    together, then every case checked against its own run."""
+    cases = ensemble()
+    ens = lbm.Ensemble([lbm.make_params(**kw) for kw in cases])
+    ens.step(130)
+    ens.sync()
+    for i, kw in enumerate(cases):
+        f_alone, forces_alone = _alone(kw, 130)
+        assert np.array_equal(ens.get_populations(i, np.float64), f_alone), i
+        assert np.array_equal(ens.forces(i)[0], forces_alone[0]), i
+
+
+def test_ensemble_reports_only_the_diverging_case():
+    cases = [dict(channel(8, u=0.05), tau=0.6), dict(nx=82, ny=42, diameter=2, u_in=0.2, tau=0.5001),
+             dict(channel(8, u=0.05), tau=0.65)]
+    ens = lbm.Ensemble([lbm.make_params(**kw) for kw in cases])
+    ens.step(3000)
+    with pytest.raises(lbm.DivergedError):
+        ens.sync()
+    assert ens.info(0)[1] == 0 and ens.info(2)[1] == 0
+    assert ens.info(1)[1] > 0
+    f_alone, _ = _alone(cases[2], 3000)
+    assert np.array_equal(ens.get_populations(2, np.float64), f_alone)
+
+
+def test_autotuner_picks_a_variant_and_caches_it(tmp_path):
+    cache = str(tmp_path / "tune.txt")
+    cases = [lbm.make_params(**channel(d, u=0.05)) for d in (8, 12, 16)]
+    ens = lbm.Ensemble(cases, tune_cache=cache)
+    v = ens.variant
+    assert 1 <= v <= lbm.num_variants()
+    text = open(cache).read().split()
+    assert len(text) == 2 and int(text[1]) == v
+    ens2 = lbm.Ensemble(cases, tune_cache=cache)  # cache hit
+    assert ens2.variant == v
+    lat = lbm.Lattice(lbm.make_params(**channel(10, u=0.05)))
+    best = lat.autotune(10, cache)
+    assert 1 <= best <= lbm.num_variants()
+    assert len(open(cache).read().split()) == 4
