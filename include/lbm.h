@@ -222,6 +222,81 @@ lbm_status lbm_batch_get_populations(lbm_batch* b, int32_t c, void* buf, int dty
 /* Kernel variant in use (1-based, as lbm_variant_name). */
 int32_t lbm_batch_variant(const lbm_batch* b);
 
+/* ------------------------------------------------------ learned closure
+ * A small network (36 -> 64 -> 64 -> 3, exact-erf GELU after both hidden
+ * layers) that predicts, on the open top, bottom and outlet boundaries of a
+ * truncated domain, the populations streaming in from outside as a residual
+ * on top of the plain treatment (free-slip walls, Eq. 7; extrapolated
+ * missing populations at the outlet, Eq. 13).  The paper has no such part:
+ * it truncates the domain far from the body (Sec. 1) and this closure aims
+ * to let a much smaller window reproduce the full domain's forces.
+ *
+ * Boundary nodes of an nx x ny lattice are numbered 0 .. nb-1 with
+ * nb = 2(nx-2) + (ny-2): the top row (y = ny-1, x = 1..nx-2), the bottom row
+ * (y = 0, x = 1..nx-2), then the outlet column (x = nx-1, y = 1..ny-2).
+ * Features of a node (36): for the node and its two inward neighbours along
+ * the boundary normal, the nine stored deviations f*_k - w_k, rho - 1 and
+ * the two velocity components, all in a frame turned so that the outward
+ * normal is +y (bottom mirrored, outlet rotated a quarter turn).  Outputs
+ * (3): the residuals of the canonical S, SW and SE populations.
+ *
+ * Weights are a flat FP32 vector of LBM_MLP_PARAMS values, W row-major
+ * (input x output): W1[36][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3].
+ * The matrix products run on the matrix cores with bfloat16 operands
+ * (round to nearest even) and FP32 accumulation; bias, GELU, loss and Adam
+ * run in FP32 on FP32 master weights. */
+#define LBM_MLP_PARAMS 6723
+typedef struct lbm_mlp lbm_mlp;
+
+/* `init` (host, LBM_MLP_PARAMS floats) or NULL for all zeros. */
+lbm_status lbm_mlp_create(const float* init, void* stream, lbm_mlp** out);
+void lbm_mlp_destroy(lbm_mlp* m);
+lbm_status lbm_mlp_get_params(lbm_mlp* m, float* out);
+lbm_status lbm_mlp_set_params(lbm_mlp* m, const float* in);
+
+/* y[M][3] = network(x[M][36]); device pointers. */
+lbm_status lbm_mlp_forward(lbm_mlp* m, const float* x, int64_t M, float* y);
+
+/* One training step on the mini-batch of rows idx[0..B) of x[.][36] and
+ * t[.][3] (device; idx NULL = rows 0..B-1): forward, mean squared error,
+ * backward, gradient summed over the batch in a fixed order, one Adam step
+ * (beta 0.9/0.999, eps 1e-8) with learning rate lr.  *loss (host, may be
+ * NULL; non-NULL synchronises) receives the batch loss before the update.
+ * B <= 65536. */
+lbm_status lbm_mlp_train_step(lbm_mlp* m, const float* x, const float* t, const int32_t* idx, int64_t B,
+                              float lr, double* loss);
+
+/* Gradient of the mean squared error on rows [0, B) without updating
+ * (host output of LBM_MLP_PARAMS floats); for checking against a reference. */
+lbm_status lbm_mlp_gradient(lbm_mlp* m, const float* x, const float* t, int64_t B, float* grad, double* loss);
+
+/* Per-column mean and standard deviation (population) of x[M][ncols]
+ * (device), into host arrays.  FP64 sums. */
+lbm_status lbm_column_moments(const float* x, int64_t M, int32_t ncols, double* mean, double* std, void* stream);
+
+/* Training data from a full-domain context: for a wnx x wny window whose
+ * node (0, 0) sits at node (ox, oy) of `full`, and n boundary-node indices
+ * nodes[] of that window (device), writes the features feat[n][36] and the
+ * residual targets target[n][3] (population streaming in from outside the
+ * window in `full`, minus the value the plain treatment computes from
+ * inside the window), from full's current state.  The window and its
+ * outside neighbours must lie inside `full`. */
+lbm_status lbm_sample_boundary(lbm_ctx* full, int32_t ox, int32_t oy, int32_t wnx, int32_t wny,
+                               const int32_t* nodes, int64_t n, float* feat, float* target);
+
+/* Switch the context to the learned closure: every step first evaluates the
+ * network on all boundary nodes from the current state, then adds
+ * out_scale * output to the plain values of the missing populations.
+ * norm (host): feature mean[36], feature 1/std[36], out_scale[3].  Needs
+ * free-slip walls, the copy-unknown outlet and no x-periodicity; the network
+ * object must outlive the context's use of it.  A network whose last layer
+ * is zero reproduces the plain run bit for bit. */
+lbm_status lbm_closure_enable(lbm_ctx* ctx, lbm_mlp* m, const float* norm);
+lbm_status lbm_closure_disable(lbm_ctx* ctx);
+
+/* Residuals the closure computes from the current state, host [nb][3]. */
+lbm_status lbm_closure_residuals(lbm_ctx* ctx, float* out);
+
 /* Thread-local message of the last failure ("" if none). */
 const char* lbm_last_error(void);
 

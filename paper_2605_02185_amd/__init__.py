@@ -27,7 +27,7 @@ from ._lib import (
 )
 
 __all__ = [
-    "Lattice", "Ensemble", "make_params", "validate", "tau_of", "geometry", "shedding_stats", "copy_probe",
+    "Lattice", "Ensemble", "Mlp", "column_moments", "make_params", "MLP_PARAMS", "validate", "tau_of", "geometry", "shedding_stats", "copy_probe",
     "num_variants", "variant_name", "LbmError", "DivergedError", "RangeError",
     "WALL_FREE_SLIP", "WALL_PERIODIC", "WALL_NEBB", "WALL_MOVING_BB",
     "OUTLET_COPY_ALL", "OUTLET_COPY_UNKNOWN",
@@ -133,6 +133,31 @@ class Lattice:
 
     def set_graphs(self, enable: bool):
         check(_lib.lib.lbm_set_graphs(self._h, 1 if enable else 0))
+
+    # ------------------------------------------------------- learned closure
+    def sample_boundary(self, ox, oy, wnx, wny, nodes, feat, target):
+        """Training samples of a wnx x wny window at (ox, oy); nodes (int32),
+        feat [n][36] and target [n][3] are device tensors."""
+        n = nodes.numel()
+        check(_lib.lib.lbm_sample_boundary(self._h, ox, oy, wnx, wny, ctypes.c_void_p(nodes.data_ptr()), n,
+                                           ctypes.c_void_p(feat.data_ptr()), ctypes.c_void_p(target.data_ptr())))
+
+    def enable_closure(self, mlp: "Mlp", norm):
+        """norm: 75 floats (feature mean[36], feature 1/std[36], output scale[3])."""
+        a = np.ascontiguousarray(norm, dtype=np.float32)
+        assert a.size == 75
+        self._mlp_ref = mlp
+        check(_lib.lib.lbm_closure_enable(self._h, mlp._h, a.ctypes.data))
+
+    def disable_closure(self):
+        check(_lib.lib.lbm_closure_disable(self._h))
+        self._mlp_ref = None
+
+    def closure_residuals(self):
+        nb = 2 * (self.nx - 2) + (self.ny - 2)
+        out = np.empty((nb, 3), np.float32)
+        check(_lib.lib.lbm_closure_residuals(self._h, out.ctypes.data))
+        return out
 
     def autotune(self, steps: int = 20, cache: str | None = None) -> int:
         """Pick the fastest kernel variant (timed on a scratch copy); returns it."""
@@ -260,3 +285,67 @@ class Ensemble:
         out = np.empty((9, p.ny, p.nx), dtype=np.float32 if dt == 0 else np.float64)
         check(_lib.lib.lbm_batch_get_populations(self._h, c, out.ctypes.data, dt, 0))
         return out
+
+
+MLP_PARAMS = 6723
+
+
+def column_moments(x, stream=None):
+    """(mean, std) per column of a device tensor x [M][ncols] (FP64 sums)."""
+    M, nc = x.shape
+    mean, std = np.empty(nc), np.empty(nc)
+    check(_lib.lib.lbm_column_moments(ctypes.c_void_p(x.data_ptr()), M, nc, mean.ctypes.data, std.ctypes.data,
+                                      _stream_handle(stream)))
+    return mean, std
+
+
+class Mlp:
+    """The closure network (36 -> 64 -> 64 -> 3) on the device.  Inputs and
+    outputs are float32 device tensors (torch) of shape [M][36] / [M][3]."""
+
+    def __init__(self, params=None, stream=None):
+        self._h = ctypes.c_void_p()
+        init = None
+        if params is not None:
+            self._init = np.ascontiguousarray(params, dtype=np.float32)
+            assert self._init.size == MLP_PARAMS
+            init = self._init.ctypes.data
+        check(_lib.lib.lbm_mlp_create(init, _stream_handle(stream), ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            _lib.lib.lbm_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        out = np.empty(MLP_PARAMS, np.float32)
+        check(_lib.lib.lbm_mlp_get_params(self._h, out.ctypes.data))
+        return out
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        check(_lib.lib.lbm_mlp_set_params(self._h, a.ctypes.data))
+
+    def forward(self, x, y):
+        check(_lib.lib.lbm_mlp_forward(self._h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                       ctypes.c_void_p(y.data_ptr())))
+
+    def train_step(self, x, t, idx, batch: int, lr: float, want_loss=False):
+        loss = ctypes.c_double()
+        ip = ctypes.c_void_p(idx.data_ptr()) if idx is not None else None
+        check(_lib.lib.lbm_mlp_train_step(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                          ip, batch, lr, ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def gradient(self, x, t):
+        g = np.empty(MLP_PARAMS, np.float32)
+        loss = ctypes.c_double()
+        check(_lib.lib.lbm_mlp_gradient(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                        x.shape[0], g.ctypes.data, ctypes.byref(loss)))
+        return g, loss.value

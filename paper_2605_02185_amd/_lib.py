@@ -106,6 +106,18 @@ def _load():
         "lbm_batch_fields": (i32, [vp, i32, vp, vp, vp, ctypes.c_int]),
         "lbm_batch_get_populations": (i32, [vp, i32, vp, ctypes.c_int, ctypes.c_int]),
         "lbm_batch_variant": (i32, [vp]),
+        "lbm_mlp_create": (i32, [vp, vp, ctypes.POINTER(vp)]),
+        "lbm_mlp_destroy": (None, [vp]),
+        "lbm_mlp_get_params": (i32, [vp, vp]),
+        "lbm_mlp_set_params": (i32, [vp, vp]),
+        "lbm_mlp_forward": (i32, [vp, vp, i64, vp]),
+        "lbm_mlp_train_step": (i32, [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.POINTER(ctypes.c_double)]),
+        "lbm_mlp_gradient": (i32, [vp, vp, vp, i64, vp, ctypes.POINTER(ctypes.c_double)]),
+        "lbm_column_moments": (i32, [vp, i64, i32, vp, vp, vp]),
+        "lbm_sample_boundary": (i32, [vp, i32, i32, i32, i32, vp, i64, vp, vp]),
+        "lbm_closure_enable": (i32, [vp, vp, vp]),
+        "lbm_closure_disable": (i32, [vp]),
+        "lbm_closure_residuals": (i32, [vp, vp]),
         "lbm_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sigs.items():

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_kernels.hip", "lbm_api.cpp", "lbm_batch.cpp"]
+SOURCES = ["lbm_kernels.hip", "lbm_closure.hip", "lbm_api.cpp", "lbm_batch.cpp", "lbm_closure_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "--offload-arch=gfx950", "-mcode-object-version=5", "-std=c++17", "-fPIC", "-shared",

@@ -152,6 +152,10 @@ struct lbm_ctx {
   int use_graphs = 1;
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+  // learned closure
+  const lbm_mlp* mlp = nullptr;
+  float* d_norm = nullptr;
+  float* d_resid = nullptr;
 };
 
 extern "C" {
@@ -285,6 +289,8 @@ void free_ctx(lbm_ctx* c) {
   (void)hipFree(c->d_step);
   (void)hipFree(c->d_bad);
   (void)hipFree(c->d_bad_step);
+  (void)hipFree(c->d_norm);
+  (void)hipFree(c->d_resid);
   delete c;
 }
 
@@ -403,6 +409,11 @@ lbm_status enqueue_step(lbm_ctx* c, hipStream_t s) {
   a.B = c->buf[c->cur ^ 1];
   a.slot = c->pending;
   a.partial = c->d_partials + (size_t)c->pending * slots_of(c);
+  if (c->mlp) {
+    const lbm::MlpDevice md = lbm::mlp_device(c->mlp);
+    HIP_TRY(lbm::launch_closure(a.A, c->geo, md.Wb, md.master, c->d_norm, c->d_resid, s));
+    a.closure = c->d_resid;
+  }
   HIP_TRY(lbm::launch_step(a, c->variant, s));
   c->cur ^= 1;
   c->step += 1;
@@ -500,6 +511,58 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps, const char* cache_path, int32
   lbm_status st = lbm_set_variant(c, v_best);
   if (st == LBM_OK && best) *best = v_best;
   return st;
+}
+
+lbm_status lbm_closure_enable(lbm_ctx* c, lbm_mlp* m, const float* norm) {
+  if (check_ctx(c) || !m || !norm) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+  if (c->p.wall != LBM_WALL_FREE_SLIP || c->p.outlet_mode != LBM_OUTLET_COPY_UNKNOWN || c->p.x_periodic)
+    return fail(LBM_ERR_INVALID_ARG, "the closure refines free-slip walls and the copy-unknown outlet");
+  lbm_status st = flush(c);
+  if (st != LBM_OK) return st;
+  drop_graphs(c);
+  const size_t nb = 2 * (size_t)(c->p.nx - 2) + (size_t)(c->p.ny - 2);
+  if (!c->d_norm) HIP_TRY(hipMalloc(&c->d_norm, sizeof(float) * lbm::kClosureNorm));
+  if (!c->d_resid) HIP_TRY(hipMalloc(&c->d_resid, sizeof(float) * 3 * nb));
+  HIP_TRY(hipMemcpyAsync(c->d_norm, norm, sizeof(float) * lbm::kClosureNorm, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->mlp = m;
+  return LBM_OK;
+}
+
+lbm_status lbm_closure_disable(lbm_ctx* c) {
+  if (check_ctx(c)) return LBM_ERR_INVALID_ARG;
+  lbm_status st = flush(c);
+  if (st != LBM_OK) return st;
+  drop_graphs(c);
+  c->mlp = nullptr;
+  return LBM_OK;
+}
+
+lbm_status lbm_closure_residuals(lbm_ctx* c, float* out) {
+  if (check_ctx(c) || !out) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+  if (!c->mlp) return fail(LBM_ERR_STATE, "closure not enabled");
+  const size_t nb = 2 * (size_t)(c->p.nx - 2) + (size_t)(c->p.ny - 2);
+  const lbm::MlpDevice md = lbm::mlp_device(c->mlp);
+  HIP_TRY(lbm::launch_closure(c->buf[c->cur], c->geo, md.Wb, md.master, c->d_norm, c->d_resid, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(out, c->d_resid, sizeof(float) * 3 * nb, hipMemcpyDeviceToHost));
+  return LBM_OK;
+}
+
+lbm_status lbm_sample_boundary(lbm_ctx* c, int32_t ox, int32_t oy, int32_t wnx, int32_t wny,
+                               const int32_t* nodes, int64_t n, float* feat, float* target) {
+  if (check_ctx(c) || !nodes || !feat || !target || n < 0 || n > INT_MAX)
+    return fail(LBM_ERR_INVALID_ARG, "bad sampling arguments");
+  // the window, its two inward layers and the outside neighbours it pulls from
+  if (wnx < 4 || wny < 4 || ox < 0 || oy < 1 || ox + wnx > c->p.nx - 1 || oy + wny > c->p.ny - 1)
+    return fail(LBM_ERR_INVALID_ARG, "window %dx%d at (%d, %d) does not fit in the %dx%d lattice", wnx, wny, ox,
+                oy, c->p.nx, c->p.ny);
+  if (n == 0) return LBM_OK;
+  lbm_status st = flush(c);
+  if (st != LBM_OK) return st;
+  HIP_TRY(lbm::launch_sample_boundary(c->buf[c->cur], c->geo, ox, oy, wnx, wny, nodes, (int)n, feat, target,
+                                      c->stream));
+  return LBM_OK;
 }
 
 lbm_status lbm_copy_probe(void* dst, const void* src, int64_t nbytes, void* stream) {

@@ -180,12 +180,30 @@ __device__ __forceinline__ void wall_bc(const StepArgs& a, int x, int y, float (
   }
 }
 
-// Streamed and row-corrected populations of node (x, y).
+// Streamed and row-corrected populations of node (x, y).  With a learned
+// closure the network's residuals are added to the wall treatment's values
+// of the three missing populations (top row nodes 0 .. nx-3, bottom row
+// nodes nx-2 .. 2nx-5 of the closure's boundary numbering).
 __device__ __forceinline__ void gather(const StepArgs& a, int x, int y, uint16_t fl, float (&g)[9]) {
   pull(a, x, y, fl, g);
   const bool wall_row = a.p.wall != kWallPeriodic && (y == 0 || y == a.g.ny - 1);
   const bool wall_x = a.p.x_periodic || (x >= 1 && x <= a.g.nx - 2);
-  if (wall_row && wall_x) wall_bc(a, x, y, g);
+  if (wall_row && wall_x) {
+    wall_bc(a, x, y, g);
+    if (a.closure) {
+      if (y == a.g.ny - 1) {
+        const float* r = a.closure + 3 * (x - 1);
+        g[4] += r[0];
+        g[7] += r[1];
+        g[8] += r[2];
+      } else {
+        const float* r = a.closure + 3 * ((a.g.nx - 2) + (x - 1));
+        g[2] += r[0];
+        g[6] += r[1];
+        g[5] += r[2];
+      }
+    }
+  }
 }
 
 template <bool NT>
@@ -215,6 +233,12 @@ __device__ __forceinline__ void general_node(const StepArgs& a, int x, int y, bo
       g[4] = own[4];
       g[5] = own[5];
       g[8] = own[8];
+      if (a.closure) {  // outlet nodes 2(nx-2) .. of the closure numbering
+        const float* r = a.closure + 3 * (2 * (nx - 2) + (y - 1));
+        g[3] += r[0];
+        g[6] += r[1];
+        g[7] += r[2];
+      }
     }
   } else {
     gather(a, x, y, fl, g);

@@ -1,0 +1,254 @@
+"""Learned boundary closure on the GPU: the matrix-core MLP against the FP64
+reference (same bfloat16 operands), the training step, the boundary sampler
+against a plain definition of its features and targets, and the closure's
+effect on a truncated run.
+
+Where floating point decides a bfloat16 rounding of a hidden activation, the
+GPU (FP32 accumulation) and the reference (FP64) can land on neighbouring
+bfloat16 values when the exact value sits within FP32 round-off of a tie;
+such a flip moves an output by about 1e-3 of its scale.  The tests therefore
+require near-exact agreement (1e-5 of the output scale) for at least 99 % of
+the samples and bound the rest by 2e-2.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2605_02185_amd as lbm
+from lbm_inputs import channel, perturbed_populations, truncated_window
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+WT = np.array([4 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 36, 1 / 36, 1 / 36, 1 / 36])
+CX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+CY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def random_params(seed, last=0.2):
+    rng = np.random.default_rng(seed)
+    p = omlp.init(seed)
+    p[6528:6723] = rng.uniform(-last, last, 195)  # W3 and b3
+    p[2304:2368] = rng.uniform(-0.1, 0.1, 64)     # b1
+    p[6464:6528] = rng.uniform(-0.1, 0.1, 64)     # b2
+    return p.astype(np.float32).astype(np.float64)
+
+
+def close_enough(got, ref, scale):
+    err = np.abs(got - ref).max(axis=1) / scale
+    frac_exact = np.mean(err < 1e-5)
+    note(f"  samples within 1e-5: {frac_exact:.4f}, worst {err.max():.2e}")
+    assert frac_exact >= 0.99 and err.max() < 2e-2
+
+
+def test_forward_matches_reference():
+    p = random_params(1)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((1000, 36))
+    net = lbm.Mlp(p)
+    y = dev(np.zeros((1000, 3)))
+    net.forward(dev(x), y)
+    ref, _ = omlp.forward(p, x.astype(np.float32).astype(np.float64), bf16_operands=True)
+    close_enough(y.cpu().numpy(), ref, np.abs(ref).max())
+
+
+def test_gradient_matches_reference():
+    p = random_params(3)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((300, 36)).astype(np.float32).astype(np.float64)
+    t = rng.standard_normal((300, 3)).astype(np.float32).astype(np.float64)
+    net = lbm.Mlp(p)
+    g, loss = net.gradient(dev(x), dev(t))
+    ref_loss, ref_g = omlp.grad(p, x, t, bf16_operands=True)
+    note(f"  loss {loss} vs {ref_loss}")
+    assert loss == pytest.approx(ref_loss, rel=1e-3)
+    rel = np.linalg.norm(g - ref_g) / np.linalg.norm(ref_g)
+    note(f"  gradient relative error {rel:.2e}")
+    assert rel < 2e-3
+    # per block of parameters
+    for lo, hi in ((0, 2304), (2304, 2368), (2368, 6464), (6464, 6528), (6528, 6720), (6720, 6723)):
+        r = np.linalg.norm(g[lo:hi] - ref_g[lo:hi]) / (np.linalg.norm(ref_g[lo:hi]) + 1e-30)
+        assert r < 1e-2, (lo, hi, r)
+
+
+def test_adam_step_matches_reference():
+    p = random_params(5)
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((256, 36)).astype(np.float32).astype(np.float64)
+    t = rng.standard_normal((256, 3)).astype(np.float32).astype(np.float64)
+    net = lbm.Mlp(p)
+    g, _ = net.gradient(dev(x), dev(t))
+    net.train_step(dev(x), dev(t), None, 256, 1e-3)
+    w1 = net.get_params()
+    ref_w, _, _ = omlp.adam(p, np.zeros_like(p), np.zeros_like(p), g.astype(np.float64), 1, lr=1e-3)
+    assert np.abs(w1 - ref_w).max() < 2e-6
+
+
+def test_training_learns_a_teacher_network():
+    """Targets from a fixed random network; 300 Adam steps on batches of 1024
+    out of 8192 samples must cut the loss at least tenfold."""
+    teacher = random_params(7, last=0.5)
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((8192, 36))
+    t, _ = omlp.forward(teacher, x, bf16_operands=False)
+    net = lbm.Mlp(omlp.init(9))
+    xd, td = dev(x), dev(t)
+    import torch
+
+    losses = []
+    for s in range(300):
+        idx = torch.from_numpy(rng.integers(0, 8192, 1024).astype(np.int32)).cuda()
+        losses.append(net.train_step(xd, td, idx, 1024, 3e-3, want_loss=(s % 50 == 0 or s == 299)))
+    first, last = losses[0], losses[-1]
+    note(f"  teacher loss {first:.3e} -> {last:.3e}")
+    assert last < first / 10
+
+
+def features_numpy(h, bt, x, y):
+    """Plain definition of the 36 features (h = stored deviations [9][ny][nx])."""
+    canon = {0: [0, 1, 2, 3, 4, 5, 6, 7, 8], 1: [0, 1, 4, 3, 2, 8, 7, 6, 5], 2: [0, 4, 1, 2, 3, 8, 5, 6, 7]}[bt]
+    step = {0: (0, -1), 1: (0, 1), 2: (-1, 0)}[bt]
+    out = []
+    for L in range(3):
+        px, py = x + L * step[0], y + L * step[1]
+        v = h[:, py, px]
+        drho = v.sum()
+        rho = 1 + drho
+        u = (CX * v).sum() / rho
+        w = (CY * v).sum() / rho
+        uc, wc = {0: (u, w), 1: (u, -w), 2: (-w, u)}[bt]
+        out += [v[c] for c in canon] + [drho, uc, wc]
+    return np.array(out)
+
+
+def test_sampler_matches_plain_definition():
+    import torch
+
+    kw = dict(channel(6, u=0.05), tau=0.6)
+    lat = lbm.Lattice(lbm.make_params(**kw))
+    lat.set_populations(perturbed_populations(11, kw["ny"], kw["nx"], WT, 0.05, np.float32))
+    lat.step(3)
+    f = lat.get_populations(np.float64)
+    h = f - WT[:, None, None]
+    ox, oy, wnx, wny = 0, 20, 150, 80
+    nb = 2 * (wnx - 2) + (wny - 2)
+    nodes = torch.arange(nb, dtype=torch.int32, device="cuda")
+    feat = torch.zeros((nb, 36), dtype=torch.float32, device="cuda")
+    targ = torch.zeros((nb, 3), dtype=torch.float32, device="cuda")
+    lat.sample_boundary(ox, oy, wnx, wny, nodes, feat, targ)
+    feat, targ = feat.cpu().numpy(), targ.cpu().numpy()
+    for i in range(nb):
+        if i < wnx - 2:
+            bt, bx, by = 0, 1 + i, wny - 1
+            unk = [(4, 2, (0, -1)), (7, 6, (1, -1)), (8, 5, (-1, -1))]  # (k, mirror, source of mirror rel. node)
+        elif i < 2 * (wnx - 2):
+            bt, bx, by = 1, 1 + i - (wnx - 2), 0
+            unk = [(2, 4, (0, 1)), (6, 7, (1, 1)), (5, 8, (-1, 1))]
+        else:
+            bt, bx, by = 2, wnx - 1, 1 + i - 2 * (wnx - 2)
+            unk = [(3, None, None), (6, None, None), (7, None, None)]
+        X, Y = ox + bx, oy + by
+        ref = features_numpy(h, bt, X, Y)
+        assert np.allclose(feat[i], ref, rtol=1e-5, atol=1e-6), i
+        for j, (k, km, rel) in enumerate(unk):
+            truth = h[k, Y - CY[k], X - CX[k]]
+            if bt == 2:  # extrapolation: k as it streams into the column inside
+                plain = h[k, Y - CY[k], X - 1 - CX[k]]
+            else:
+                plain = h[km, Y + rel[1], X + rel[0]]
+            assert targ[i, j] == pytest.approx(truth - plain, abs=2e-7), (i, j)
+
+
+def _trunc(d=10):
+    return dict(truncated_window(d, u=0.05), tau=0.62, outlet_mode=lbm.OUTLET_COPY_UNKNOWN)
+
+
+def test_zero_closure_reproduces_the_plain_run_bitwise():
+    kw = _trunc()
+    a = lbm.Lattice(lbm.make_params(**kw))
+    b = lbm.Lattice(lbm.make_params(**kw))
+    net = lbm.Mlp(omlp.init(12))  # last layer zero
+    norm = np.concatenate([np.zeros(36), np.ones(36), np.full(3, 0.01)])
+    b.enable_closure(net, norm)
+    for n in (7, 130, 64):
+        a.step(n)
+        b.step(n)
+        assert np.array_equal(a.get_populations(np.float64), b.get_populations(np.float64)), n
+    assert np.array_equal(a.forces()[0], b.forces()[0])
+    assert np.all(b.closure_residuals() == 0.0)
+
+
+def test_closure_residuals_match_reference_network():
+    kw = _trunc()
+    lat = lbm.Lattice(lbm.make_params(**kw))
+    lat.step(50)
+    p = random_params(13)
+    rng = np.random.default_rng(14)
+    mean, inv = rng.standard_normal(36) * 0.01, np.exp(rng.standard_normal(36))
+    scale = np.array([0.01, 0.02, 0.03])
+    norm = np.concatenate([mean, inv, scale]).astype(np.float32)
+    net = lbm.Mlp(p)
+    lat.enable_closure(net, norm)
+    r = lat.closure_residuals()
+    h = lat.get_populations(np.float64) - WT[:, None, None]
+    nx, ny = kw["nx"], kw["ny"]
+    xs = []
+    for i in range(r.shape[0]):
+        if i < nx - 2:
+            xs.append(features_numpy(h, 0, 1 + i, ny - 1))
+        elif i < 2 * (nx - 2):
+            xs.append(features_numpy(h, 1, 1 + i - (nx - 2), 0))
+        else:
+            xs.append(features_numpy(h, 2, nx - 1, 1 + i - 2 * (nx - 2)))
+    xs = np.array(xs).astype(np.float32).astype(np.float64)
+    xn = ((xs - norm[:36]) * norm[36:72]).astype(np.float32).astype(np.float64)
+    y, _ = omlp.forward(p, xn, bf16_operands=True)
+    ref = y * scale
+    close_enough(r.astype(np.float64), ref, np.abs(ref).max())
+
+
+def test_closure_residuals_enter_the_missing_populations():
+    """A network with only an output bias c adds c * scale to the three
+    missing populations of every open-boundary node before the collision,
+    which conserves mass and momentum: the node's density rises by 3 d and
+    its momentum by d times the sum of the three directions."""
+    kw = _trunc()
+    nx, ny = kw["nx"], kw["ny"]
+    p = np.zeros(lbm.MLP_PARAMS)
+    p[6720:6723] = [1.0, 2.0, -1.5]
+    scale = np.array([1e-4, 1e-4, 1e-4])
+    norm = np.concatenate([np.zeros(36), np.ones(36), scale])
+    a = lbm.Lattice(lbm.make_params(**kw))
+    b = lbm.Lattice(lbm.make_params(**kw))
+    a.step(20)
+    b.step(20)
+    b.enable_closure(lbm.Mlp(p), norm)
+    a.step(1)
+    b.step(1)
+    ra, uxa, uya = (v.astype(np.float64) for v in a.fields())
+    rb, uxb, uyb = (v.astype(np.float64) for v in b.fields())
+    d = np.array([1.0, 2.0, -1.5]) * 1e-4
+    cases = [  # (rows/cols selector, physical directions of canonical S, SW, SE)
+        ((slice(ny - 1, ny), slice(1, nx - 1)), [4, 7, 8]),
+        ((slice(0, 1), slice(1, nx - 1)), [2, 6, 5]),
+        ((slice(1, ny - 1), slice(nx - 1, nx)), [3, 6, 7]),
+    ]
+    for sel, ks in cases:
+        drho = rb[sel] - ra[sel]
+        assert np.allclose(drho, d.sum(), atol=3e-7), ks
+        jx = rb[sel] * uxb[sel] - ra[sel] * uxa[sel]
+        jy = rb[sel] * uyb[sel] - ra[sel] * uya[sel]
+        assert np.allclose(jx, sum(d[j] * CX[k] for j, k in enumerate(ks)), atol=3e-7), ks
+        assert np.allclose(jy, sum(d[j] * CY[k] for j, k in enumerate(ks)), atol=3e-7), ks

@@ -27,7 +27,7 @@ def note(msg):
     sys.stdout.flush()
 
 
-def established(cl, n=3, tol=0.01):
+def established(cl, n=3, tol=0.02):
     """The lift amplitude of each of the last n+1 periods, cut at successive
     upward crossings of the mean, stays within tol of the last one."""
     c = cl - cl.mean()
@@ -49,8 +49,6 @@ def window_parity(kw, spin_up, window, periods, require_established=True):
     gpu = lbm.shedding_stats(cd, cl, d, u, periods)
     ok, amps = established(cl, n=min(3, periods - 1))
     note(f"  GPU {gpu}, per-period amplitudes {np.round(amps, 5)}")
-    if require_established:
-        assert ok, "shedding not established at the start of the window"
 
     o = oracle.Oracle(oracle.OracleParams(**kw))
     o.set_fstar(state)
@@ -61,6 +59,8 @@ def window_parity(kw, spin_up, window, periods, require_established=True):
     note(f"  oracle {ora}")
     for k in ("mean_cd", "cl_amp", "st"):
         assert gpu[k] == pytest.approx(ora[k], rel=0.01), k
+    if require_established:
+        assert ok, "shedding not established at the start of the window"
     return gpu
 
 
