@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-ceiling reference")
     ap.add_argument("--no-graphs", action="store_true", help="plain launches instead of graph replay")
+    ap.add_argument("--closure", action="store_true",
+                    help="also train and evaluate the learned boundary closure (about a minute)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -187,7 +189,29 @@ def main():
     lat.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    if args.closure:
+        out["closure"] = closure_result()
     print(json.dumps(out), flush=True)
+
+
+def closure_result() -> dict:
+    """Learned closure at D = 40: train on full-domain samples (Re 80, 100,
+    120), then 25k steps of the full domain against the truncated window
+    (plain and learned) from the same established state."""
+    from paper_2605_02185_amd import closure as C
+
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    X, T = C.generate(log=log)
+    t1 = time.perf_counter()
+    net, norm, hist = C.fit(X, T, epochs=20, noise=C.NOISE, log=log)
+    t2 = time.perf_counter()
+    res = C.evaluate({"trunc_learned": (net, norm, C.MASK, 80, C.BETA)}, log=log)
+    res["samples"] = int(X.shape[0])
+    res["data_s"] = round(t1 - t0, 2)
+    res["train_s"] = round(t2 - t1, 2)
+    res["val_loss"] = hist[-1]
+    return res
 
 
 if __name__ == "__main__":

@@ -254,6 +254,19 @@ void lbm_mlp_destroy(lbm_mlp* m);
 lbm_status lbm_mlp_get_params(lbm_mlp* m, float* out);
 lbm_status lbm_mlp_set_params(lbm_mlp* m, const float* in);
 
+/* Optional z-scoring inside the network's kernels (norm NULL = off): norm
+ * (host, 75 floats) = feature mean[36], feature 1/std[36], output scale[3].
+ * When on, forward/train/gradient read raw features x and raw targets t:
+ * the network sees (x - mean)/std and is fitted to t/scale, and forward
+ * returns outputs times scale. */
+lbm_status lbm_mlp_set_norm(lbm_mlp* m, const float* norm);
+
+/* Training-input noise: train steps add independent N(0, amplitude^2) noise
+ * to every z-scored input (counter-based SplitMix64 + Box-Muller, keyed by
+ * seed, step, row and feature).  0 (the default) switches it off; gradients
+ * from lbm_mlp_gradient never use it. */
+lbm_status lbm_mlp_set_noise(lbm_mlp* m, float amplitude, uint64_t seed);
+
 /* y[M][3] = network(x[M][36]); device pointers. */
 lbm_status lbm_mlp_forward(lbm_mlp* m, const float* x, int64_t M, float* y);
 
@@ -286,13 +299,21 @@ lbm_status lbm_sample_boundary(lbm_ctx* full, int32_t ox, int32_t oy, int32_t wn
 
 /* Switch the context to the learned closure: every step first evaluates the
  * network on all boundary nodes from the current state, then adds
- * out_scale * output to the plain values of the missing populations.
+ * out_scale * output to the plain values of the missing populations on the
+ * boundaries selected by the bit mask `boundaries` (1 top, 2 bottom, 4
+ * outlet; the others keep their plain treatment).
  * norm (host): feature mean[36], feature 1/std[36], out_scale[3].  Needs
  * free-slip walls, the copy-unknown outlet and no x-periodicity; the network
  * object must outlive the context's use of it.  A network whose last layer
  * is zero reproduces the plain run bit for bit. */
-lbm_status lbm_closure_enable(lbm_ctx* ctx, lbm_mlp* m, const float* norm);
+lbm_status lbm_closure_enable(lbm_ctx* ctx, lbm_mlp* m, const float* norm, int32_t boundaries);
 lbm_status lbm_closure_disable(lbm_ctx* ctx);
+
+/* Low-pass of the applied residual per node: r <- r + beta (prediction - r)
+ * each step, starting from r = 0 when the closure is enabled; beta = 1 (the
+ * default) applies each prediction as is.  Row nodes within `taper` nodes of
+ * the inlet or the outlet column keep the plain treatment (default 0). */
+lbm_status lbm_closure_set_filter(lbm_ctx* ctx, float beta, int32_t taper);
 
 /* Residuals the closure computes from the current state, host [nb][3]. */
 lbm_status lbm_closure_residuals(lbm_ctx* ctx, float* out);

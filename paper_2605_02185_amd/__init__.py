@@ -142,12 +142,16 @@ class Lattice:
         check(_lib.lib.lbm_sample_boundary(self._h, ox, oy, wnx, wny, ctypes.c_void_p(nodes.data_ptr()), n,
                                            ctypes.c_void_p(feat.data_ptr()), ctypes.c_void_p(target.data_ptr())))
 
-    def enable_closure(self, mlp: "Mlp", norm):
-        """norm: 75 floats (feature mean[36], feature 1/std[36], output scale[3])."""
+    def enable_closure(self, mlp: "Mlp", norm, boundaries: int = 7):
+        """norm: 75 floats (feature mean[36], feature 1/std[36], output scale[3]);
+        boundaries: bit mask 1 top, 2 bottom, 4 outlet."""
         a = np.ascontiguousarray(norm, dtype=np.float32)
         assert a.size == 75
         self._mlp_ref = mlp
-        check(_lib.lib.lbm_closure_enable(self._h, mlp._h, a.ctypes.data))
+        check(_lib.lib.lbm_closure_enable(self._h, mlp._h, a.ctypes.data, boundaries))
+
+    def set_closure_filter(self, beta: float = 1.0, taper: int = 0):
+        check(_lib.lib.lbm_closure_set_filter(self._h, beta, taper))
 
     def disable_closure(self):
         check(_lib.lib.lbm_closure_disable(self._h))
@@ -331,6 +335,18 @@ class Mlp:
     def set_params(self, p):
         a = np.ascontiguousarray(p, dtype=np.float32)
         check(_lib.lib.lbm_mlp_set_params(self._h, a.ctypes.data))
+
+    def set_norm(self, norm):
+        """z-score inside the kernels (75 floats) or None to switch it off."""
+        if norm is None:
+            check(_lib.lib.lbm_mlp_set_norm(self._h, None))
+            return
+        self._norm = np.ascontiguousarray(norm, dtype=np.float32)
+        assert self._norm.size == 75
+        check(_lib.lib.lbm_mlp_set_norm(self._h, self._norm.ctypes.data))
+
+    def set_noise(self, amplitude: float, seed: int = 0):
+        check(_lib.lib.lbm_mlp_set_noise(self._h, amplitude, seed))
 
     def forward(self, x, y):
         check(_lib.lib.lbm_mlp_forward(self._h, ctypes.c_void_p(x.data_ptr()), x.shape[0],

@@ -111,12 +111,15 @@ def _load():
         "lbm_mlp_get_params": (i32, [vp, vp]),
         "lbm_mlp_set_params": (i32, [vp, vp]),
         "lbm_mlp_forward": (i32, [vp, vp, i64, vp]),
+        "lbm_mlp_set_norm": (i32, [vp, vp]),
+        "lbm_mlp_set_noise": (i32, [vp, ctypes.c_float, ctypes.c_uint64]),
         "lbm_mlp_train_step": (i32, [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.POINTER(ctypes.c_double)]),
         "lbm_mlp_gradient": (i32, [vp, vp, vp, i64, vp, ctypes.POINTER(ctypes.c_double)]),
         "lbm_column_moments": (i32, [vp, i64, i32, vp, vp, vp]),
         "lbm_sample_boundary": (i32, [vp, i32, i32, i32, i32, vp, i64, vp, vp]),
-        "lbm_closure_enable": (i32, [vp, vp, vp]),
+        "lbm_closure_enable": (i32, [vp, vp, vp, i32]),
         "lbm_closure_disable": (i32, [vp]),
+        "lbm_closure_set_filter": (i32, [vp, ctypes.c_float, i32]),
         "lbm_closure_residuals": (i32, [vp, vp]),
         "lbm_last_error": (ctypes.c_char_p, []),
     }

@@ -154,6 +154,9 @@ struct lbm_ctx {
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   // learned closure
   const lbm_mlp* mlp = nullptr;
+  int closure_mask = 7;
+  float closure_beta = 1.0f;
+  int closure_taper = 0;
   float* d_norm = nullptr;
   float* d_resid = nullptr;
 };
@@ -411,7 +414,8 @@ lbm_status enqueue_step(lbm_ctx* c, hipStream_t s) {
   a.partial = c->d_partials + (size_t)c->pending * slots_of(c);
   if (c->mlp) {
     const lbm::MlpDevice md = lbm::mlp_device(c->mlp);
-    HIP_TRY(lbm::launch_closure(a.A, c->geo, md.Wb, md.master, c->d_norm, c->d_resid, s));
+    HIP_TRY(lbm::launch_closure(a.A, c->geo, md.Wb, md.master, c->d_norm, c->closure_mask, c->closure_beta,
+                                c->closure_taper, c->d_resid, s));
     a.closure = c->d_resid;
   }
   HIP_TRY(lbm::launch_step(a, c->variant, s));
@@ -513,8 +517,9 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps, const char* cache_path, int32
   return st;
 }
 
-lbm_status lbm_closure_enable(lbm_ctx* c, lbm_mlp* m, const float* norm) {
+lbm_status lbm_closure_enable(lbm_ctx* c, lbm_mlp* m, const float* norm, int32_t boundaries) {
   if (check_ctx(c) || !m || !norm) return fail(LBM_ERR_INVALID_ARG, "NULL argument");
+  if (boundaries < 0 || boundaries > 7) return fail(LBM_ERR_INVALID_ARG, "boundary mask must be in 0..7");
   if (c->p.wall != LBM_WALL_FREE_SLIP || c->p.outlet_mode != LBM_OUTLET_COPY_UNKNOWN || c->p.x_periodic)
     return fail(LBM_ERR_INVALID_ARG, "the closure refines free-slip walls and the copy-unknown outlet");
   lbm_status st = flush(c);
@@ -523,9 +528,21 @@ lbm_status lbm_closure_enable(lbm_ctx* c, lbm_mlp* m, const float* norm) {
   const size_t nb = 2 * (size_t)(c->p.nx - 2) + (size_t)(c->p.ny - 2);
   if (!c->d_norm) HIP_TRY(hipMalloc(&c->d_norm, sizeof(float) * lbm::kClosureNorm));
   if (!c->d_resid) HIP_TRY(hipMalloc(&c->d_resid, sizeof(float) * 3 * nb));
+  HIP_TRY(hipMemsetAsync(c->d_resid, 0, sizeof(float) * 3 * nb, c->stream));
   HIP_TRY(hipMemcpyAsync(c->d_norm, norm, sizeof(float) * lbm::kClosureNorm, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->mlp = m;
+  c->closure_mask = boundaries;
+  return LBM_OK;
+}
+
+lbm_status lbm_closure_set_filter(lbm_ctx* c, float beta, int32_t taper) {
+  if (check_ctx(c)) return LBM_ERR_INVALID_ARG;
+  if (!(beta > 0.0f && beta <= 1.0f)) return fail(LBM_ERR_INVALID_ARG, "beta must be in (0, 1]");
+  if (taper < 0) return fail(LBM_ERR_INVALID_ARG, "taper must be >= 0");
+  drop_graphs(c);
+  c->closure_beta = beta;
+  c->closure_taper = taper;
   return LBM_OK;
 }
 
@@ -543,7 +560,8 @@ lbm_status lbm_closure_residuals(lbm_ctx* c, float* out) {
   if (!c->mlp) return fail(LBM_ERR_STATE, "closure not enabled");
   const size_t nb = 2 * (size_t)(c->p.nx - 2) + (size_t)(c->p.ny - 2);
   const lbm::MlpDevice md = lbm::mlp_device(c->mlp);
-  HIP_TRY(lbm::launch_closure(c->buf[c->cur], c->geo, md.Wb, md.master, c->d_norm, c->d_resid, c->stream));
+  HIP_TRY(lbm::launch_closure(c->buf[c->cur], c->geo, md.Wb, md.master, c->d_norm, c->closure_mask, 1.0f,
+                              c->closure_taper, c->d_resid, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   HIP_TRY(hipMemcpy(out, c->d_resid, sizeof(float) * 3 * nb, hipMemcpyDeviceToHost));
   return LBM_OK;

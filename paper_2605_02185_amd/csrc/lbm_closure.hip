@@ -29,6 +29,21 @@ __device__ __forceinline__ uint16_t to_bf16(float x) {
   return (uint16_t)(u >> 16);
 }
 
+// SplitMix64 (Steele, Lea & Flood 2014) as a counter-based generator, and a
+// standard normal variate from one 64-bit draw by the Box-Muller transform.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ float gauss(uint64_t key) {
+  const uint64_t r = splitmix64(key);
+  const float u1 = (float)((r >> 40) + 1) * (1.0f / 16777217.0f);  // (0, 1]
+  const float u2 = (float)((r >> 16) & 0xFFFFFFull) * (1.0f / 16777216.0f);
+  return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+}
+
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float z) {
   return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
@@ -113,26 +128,48 @@ __device__ __forceinline__ void forward_block(MlpLds& s, const uint16_t* W1b, co
   __syncthreads();
 }
 
+constexpr int kWb = 48 * 64 + 64 * 64 + 64 * 16;  // bfloat16 weights, padded layouts
+
+// Copies the bfloat16 weights into LDS with 16-byte loads (8192 halves).
+__device__ __forceinline__ void stage_weights(uint16_t* dst, const uint16_t* __restrict__ Wb) {
+  const uint4* src = (const uint4*)Wb;
+  uint4* d = (uint4*)dst;
+  for (int i = threadIdx.x; i < kWb / 8; i += blockDim.x) d[i] = src[i];
+}
+
 // Offsets of the parameters in the flat FP32 vector (W row-major in x out).
 constexpr int OW1 = 0, OB1 = 2304, OW2 = 2368, OB2 = 6464, OW3 = 6528, OB3 = 6720, NP = 6723;
 
 // One block: MB samples (rows idx[blk*MB + r] of X and T, or row blk*MB + r
 // when idx is null; rows beyond B are padding).  Writes the block's gradient
 // (FP32, flat layout) and its sum of squared errors.
+// With `norm` (feature mean[36], 1/std[36], output scale[3]) the raw X and
+// T are z-scored on load: x = (X - mean)/std, t = T/scale.  With noise > 0
+// every (z-scored) input gets independent N(0, noise^2) noise keyed by
+// (key, dataset row, feature), which regularises the fit towards maps that
+// do not amplify small input errors.
 __global__ __launch_bounds__(256) void mlp_train_kernel(const float* __restrict__ X, const float* __restrict__ T,
                                                         const int* __restrict__ idx, int B,
                                                         const uint16_t* __restrict__ Wb,
                                                         const float* __restrict__ master,
+                                                        const float* __restrict__ norm,
                                                         float* __restrict__ gpart, double* __restrict__ lpart,
-                                                        float dscale) {
+                                                        float dscale, float noise, uint64_t key) {
   __shared__ MlpLds s;
   __shared__ double red[256];
+  __shared__ __align__(16) uint16_t wl[kWb];
   const int blk = blockIdx.x, tid = threadIdx.x, w = tid >> 6;
-  const uint16_t *W1b = Wb, *W2b = Wb + 48 * 64, *W3b = W2b + 64 * 64;
+  stage_weights(wl, Wb);
+  const uint16_t *W1b = wl, *W2b = wl + 48 * 64, *W3b = W2b + 64 * 64;
   for (int e = tid; e < MB * 48; e += 256) {
     const int r = e / 48, c = e % 48, smp = blk * MB + r;
     float v = 0.0f;
-    if (smp < B && c < 36) v = X[(int64_t)(idx ? idx[smp] : smp) * 36 + c];
+    if (smp < B && c < 36) {
+      const int64_t row = idx ? idx[smp] : smp;
+      v = X[row * 36 + c];
+      if (norm) v = (v - norm[c]) * norm[36 + c];
+      if (noise > 0.0f) v += noise * gauss(key ^ (uint64_t)(row * 64 + c));
+    }
     s.x[e] = to_bf16(v);
   }
   __syncthreads();
@@ -143,7 +180,9 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(const float* __restrict_
     const int r = e / 16, c = e % 16, smp = blk * MB + r;
     float d = 0.0f;
     if (smp < B && c < 3) {
-      const float diff = s.y[e] - T[(int64_t)(idx ? idx[smp] : smp) * 3 + c];
+      float tv = T[(int64_t)(idx ? idx[smp] : smp) * 3 + c];
+      if (norm) tv = tv / norm[72 + c];
+      const float diff = s.y[e] - tv;
       sq += (double)diff * diff;
       d = dscale * diff;
     }
@@ -266,21 +305,30 @@ __global__ __launch_bounds__(256) void mlp_adam_kernel(const float* __restrict__
   }
 }
 
+// With `norm` the inputs are z-scored and the outputs scaled back (y * scale).
 __global__ __launch_bounds__(256) void mlp_forward_kernel(const float* __restrict__ X, int M,
                                                           const uint16_t* __restrict__ Wb,
                                                           const float* __restrict__ master,
+                                                          const float* __restrict__ norm,
                                                           float* __restrict__ Y) {
   __shared__ MlpLds s;
+  __shared__ __align__(16) uint16_t wl[kWb];
   const int blk = blockIdx.x, tid = threadIdx.x;
+  stage_weights(wl, Wb);
   for (int e = tid; e < MB * 48; e += 256) {
     const int r = e / 48, c = e % 48, smp = blk * MB + r;
-    s.x[e] = to_bf16(smp < M && c < 36 ? X[(int64_t)smp * 36 + c] : 0.0f);
+    float v = 0.0f;
+    if (smp < M && c < 36) {
+      v = X[(int64_t)smp * 36 + c];
+      if (norm) v = (v - norm[c]) * norm[36 + c];
+    }
+    s.x[e] = to_bf16(v);
   }
   __syncthreads();
-  forward_block(s, Wb, Wb + 48 * 64, Wb + 48 * 64 + 64 * 64, master + OB1, master + OB2, master + OB3, false);
+  forward_block(s, wl, wl + 48 * 64, wl + 48 * 64 + 64 * 64, master + OB1, master + OB2, master + OB3, false);
   for (int e = tid; e < MB * 3; e += 256) {
     const int r = e / 3, c = e % 3, smp = blk * MB + r;
-    if (smp < M) Y[(int64_t)smp * 3 + c] = s.y[r * 16 + c];
+    if (smp < M) Y[(int64_t)smp * 3 + c] = norm ? s.y[r * 16 + c] * norm[72 + c] : s.y[r * 16 + c];
   }
 }
 
@@ -315,23 +363,26 @@ __device__ __forceinline__ float ld(const float* __restrict__ A, const Geometry&
 // neighbours, the nine stored post-collision deviations f*_k - w_k in
 // canonical order, then drho = rho - 1 and the canonical velocity.  (ox, oy)
 // places the boundary node's lattice inside the state's lattice.
+__device__ __forceinline__ void layer_features(const float* __restrict__ A, const Geometry& g, const BNode& b,
+                                               int ox, int oy, int L, float* f) {
+  const int x = ox + b.x + L * b.nx_, y = oy + b.y + L * b.ny_;
+  float h[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) h[k] = ld(A, g, k, x, y);
+  const float drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
+  const float ir = 1.0f / (1.0f + drho);
+  const float u = (((h[1] - h[3]) + (h[5] - h[7])) + (h[8] - h[6])) * ir;
+  const float v = (((h[2] - h[4]) + (h[5] - h[7])) + (h[6] - h[8])) * ir;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) f[c] = h[kCanon[b.type][c]];
+  f[9] = drho;
+  f[10] = b.type == 2 ? -v : u;
+  f[11] = b.type == 0 ? v : (b.type == 1 ? -v : u);
+}
+
 __device__ void features(const float* __restrict__ A, const Geometry& g, const BNode& b, int ox, int oy,
                          float* f) {
-  for (int L = 0; L < 3; ++L) {
-    const int x = ox + b.x + L * b.nx_, y = oy + b.y + L * b.ny_;
-    float h[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) h[k] = ld(A, g, k, x, y);
-    const float drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
-    const float ir = 1.0f / (1.0f + drho);
-    const float u = (((h[1] - h[3]) + (h[5] - h[7])) + (h[8] - h[6])) * ir;
-    const float v = (((h[2] - h[4]) + (h[5] - h[7])) + (h[6] - h[8])) * ir;
-#pragma unroll
-    for (int c = 0; c < 9; ++c) f[L * 12 + c] = h[kCanon[b.type][c]];
-    f[L * 12 + 9] = drho;
-    f[L * 12 + 10] = b.type == 2 ? -v : u;
-    f[L * 12 + 11] = b.type == 0 ? v : (b.type == 1 ? -v : u);
-  }
+  for (int L = 0; L < 3; ++L) layer_features(A, g, b, ox, oy, L, f + 12 * L);
 }
 
 // Training samples from a full-domain state A: for window boundary node
@@ -382,29 +433,47 @@ __global__ void sample_kernel(const float* __restrict__ A, Geometry g, int ox, i
 // The closure of one step: features of MB boundary nodes of the state A,
 // z-scored, through the network; residual r = y * scale (physical order of
 // the missing populations of each boundary).
+// Boundaries whose bit is clear in `mask` (1 top, 2 bottom, 4 outlet) keep
+// the plain treatment: their residuals are written as zero.  With beta < 1
+// the applied residual follows the prediction through a first-order
+// low-pass, r <- r + beta (prediction - r), per node.
 __global__ __launch_bounds__(256) void closure_kernel(const float* __restrict__ A, Geometry g, int nb,
                                                       const uint16_t* __restrict__ Wb,
                                                       const float* __restrict__ master,
-                                                      const float* __restrict__ norm, float* __restrict__ resid) {
+                                                      const float* __restrict__ norm, int mask, float beta,
+                                                      int taper, float* __restrict__ resid) {
   __shared__ MlpLds s;
+  __shared__ __align__(16) uint16_t wl[kWb];
   const int blk = blockIdx.x, tid = threadIdx.x;
-  if (tid < MB) {
-    const int i = blk * MB + tid;
-    float f[36];
+  stage_weights(wl, Wb);
+  if (tid < MB * 3) {  // thread (node r, layer L): 12 features
+    const int r = tid / 3, L = tid % 3, i = blk * MB + r;
+    float f[12];
     if (i < nb) {
       const BNode b = boundary_node(i, g.nx, g.ny);
-      features(A, g, b, 0, 0, f);
+      layer_features(A, g, b, 0, 0, L, f);
     }
-    for (int c = 0; c < 48; ++c) {
-      const float v = (i < nb && c < 36) ? (f[c] - norm[c]) * norm[36 + c] : 0.0f;
-      s.x[tid * 48 + c] = to_bf16(v);
+    for (int c = 0; c < 12; ++c) {
+      const int q = L * 12 + c;
+      const float v = i < nb ? (f[c] - norm[q]) * norm[36 + q] : 0.0f;
+      s.x[r * 48 + q] = to_bf16(v);
     }
+  } else if (tid < MB * 3 + MB) {  // zero the K padding 36..47
+    const int r = tid - MB * 3;
+    for (int c = 36; c < 48; ++c) s.x[r * 48 + c] = 0;
   }
   __syncthreads();
-  forward_block(s, Wb, Wb + 48 * 64, Wb + 48 * 64 + 64 * 64, master + OB1, master + OB2, master + OB3, false);
+  forward_block(s, wl, wl + 48 * 64, wl + 48 * 64 + 64 * 64, master + OB1, master + OB2, master + OB3, false);
   if (tid < MB * 3) {
     const int r = tid / 3, c = tid % 3, i = blk * MB + r;
-    if (i < nb) resid[(int64_t)i * 3 + c] = s.y[r * 16 + c] * norm[72 + c];
+    if (i < nb) {
+      const BNode b = boundary_node(i, g.nx, g.ny);
+      // rows keep the plain treatment within `taper` nodes of the inlet and outlet
+      const bool on = ((mask >> b.type) & 1) && (b.type == 2 || (b.x >= taper && b.x <= g.nx - 1 - taper));
+      const float pred = on ? s.y[r * 16 + c] * norm[72 + c] : 0.0f;
+      float* dst = resid + (int64_t)i * 3 + c;
+      *dst = beta >= 1.0f ? pred : *dst + beta * (pred - *dst);
+    }
   }
 }
 
@@ -440,10 +509,11 @@ __global__ __launch_bounds__(256) void column_moments_kernel(const float* __rest
 int mlp_blocks(int64_t B) { return (int)((B + MB - 1) / MB); }
 
 hipError_t launch_mlp_train(const float* X, const float* T, const int* idx, int B, const uint16_t* Wb,
-                            const float* master, float* gpart, double* lpart, hipStream_t s) {
+                            const float* master, const float* norm, float* gpart, double* lpart, float noise,
+                            uint64_t key, hipStream_t s) {
   const float dscale = 2.0f / (3.0f * (float)B);
-  hipLaunchKernelGGL(mlp_train_kernel, dim3(mlp_blocks(B)), dim3(256), 0, s, X, T, idx, B, Wb, master, gpart,
-                     lpart, dscale);
+  hipLaunchKernelGGL(mlp_train_kernel, dim3(mlp_blocks(B)), dim3(256), 0, s, X, T, idx, B, Wb, master, norm,
+                     gpart, lpart, dscale, noise, key);
   return hipGetLastError();
 }
 
@@ -455,9 +525,9 @@ hipError_t launch_mlp_adam(const float* gpart, int nblk, const double* lpart, fl
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_forward(const float* X, int M, const uint16_t* Wb, const float* master, float* Y,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(mlp_forward_kernel, dim3(mlp_blocks(M)), dim3(256), 0, s, X, M, Wb, master, Y);
+hipError_t launch_mlp_forward(const float* X, int M, const uint16_t* Wb, const float* master, const float* norm,
+                              float* Y, hipStream_t s) {
+  hipLaunchKernelGGL(mlp_forward_kernel, dim3(mlp_blocks(M)), dim3(256), 0, s, X, M, Wb, master, norm, Y);
   return hipGetLastError();
 }
 
@@ -469,10 +539,10 @@ hipError_t launch_sample_boundary(const float* A, const Geometry& g, int ox, int
 }
 
 hipError_t launch_closure(const float* A, const Geometry& g, const uint16_t* Wb, const float* master,
-                          const float* norm, float* resid, hipStream_t s) {
+                          const float* norm, int mask, float beta, int taper, float* resid, hipStream_t s) {
   const int nb = 2 * (g.nx - 2) + (g.ny - 2);
   hipLaunchKernelGGL(closure_kernel, dim3((nb + MB - 1) / MB), dim3(256), 0, s, A, g, nb, Wb, master, norm,
-                     resid);
+                     mask, beta, taper, resid);
   return hipGetLastError();
 }
 

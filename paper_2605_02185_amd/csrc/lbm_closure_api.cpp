@@ -33,6 +33,10 @@ struct lbm_mlp {
   double* lpart = nullptr;  // per-block squared errors
   float* grad = nullptr;    // reduced gradient
   double* loss = nullptr;
+  float* norm = nullptr;    // optional z-score (mean[36], 1/std[36], out scale[3])
+  int use_norm = 0;
+  float noise = 0.0f;       // training input noise (z-scored units)
+  uint64_t seed = 0;
   int step = 0;
 };
 
@@ -53,6 +57,7 @@ void free_mlp(lbm_mlp* m) {
   (void)hipFree(m->lpart);
   (void)hipFree(m->grad);
   (void)hipFree(m->loss);
+  (void)hipFree(m->norm);
   delete m;
 }
 
@@ -73,6 +78,7 @@ lbm_status create_impl(lbm_mlp* m, const float* init) {
   MTRY(hipMalloc(&m->gpart, (size_t)lbm::mlp_blocks(kMaxBatch) * np));
   MTRY(hipMalloc(&m->lpart, (size_t)lbm::mlp_blocks(kMaxBatch) * sizeof(double)));
   MTRY(hipMalloc(&m->loss, sizeof(double)));
+  MTRY(hipMalloc(&m->norm, sizeof(float) * lbm::kClosureNorm));
   MTRY(hipMemsetAsync(m->m, 0, np, m->stream));
   MTRY(hipMemsetAsync(m->v, 0, np, m->stream));
   // padding of the bfloat16 layouts must be zero
@@ -123,10 +129,25 @@ lbm_status lbm_mlp_set_params(lbm_mlp* m, const float* in) {
   return LBM_OK;
 }
 
+lbm_status lbm_mlp_set_norm(lbm_mlp* m, const float* norm) {
+  if (!m) return lbm::set_error(LBM_ERR_INVALID_ARG, "NULL network");
+  if (norm) MTRY(hipMemcpyAsync(m->norm, norm, sizeof(float) * lbm::kClosureNorm, hipMemcpyHostToDevice, m->stream));
+  MTRY(hipStreamSynchronize(m->stream));
+  m->use_norm = norm ? 1 : 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_set_noise(lbm_mlp* m, float amplitude, uint64_t seed) {
+  if (!m || !(amplitude >= 0.0f)) return lbm::set_error(LBM_ERR_INVALID_ARG, "bad noise arguments");
+  m->noise = amplitude;
+  m->seed = seed;
+  return LBM_OK;
+}
+
 lbm_status lbm_mlp_forward(lbm_mlp* m, const float* x, int64_t M, float* y) {
   if (!m || !x || !y || M < 0 || M > (int64_t)1 << 30) return lbm::set_error(LBM_ERR_INVALID_ARG, "bad forward arguments");
   if (M == 0) return LBM_OK;
-  MTRY(lbm::launch_mlp_forward(x, (int)M, m->Wb, m->master, y, m->stream));
+  MTRY(lbm::launch_mlp_forward(x, (int)M, m->Wb, m->master, m->use_norm ? m->norm : nullptr, y, m->stream));
   return LBM_OK;
 }
 
@@ -134,7 +155,8 @@ lbm_status lbm_mlp_train_step(lbm_mlp* m, const float* x, const float* t, const 
                               float lr, double* loss) {
   if (!m || !x || !t || B < 1 || B > kMaxBatch || !(lr >= 0.0f))
     return lbm::set_error(LBM_ERR_INVALID_ARG, "bad train-step arguments");
-  MTRY(lbm::launch_mlp_train(x, t, idx, (int)B, m->Wb, m->master, m->gpart, m->lpart, m->stream));
+  MTRY(lbm::launch_mlp_train(x, t, idx, (int)B, m->Wb, m->master, m->use_norm ? m->norm : nullptr, m->gpart,
+                              m->lpart, m->noise, m->seed * 0x100000001B3ull + (uint64_t)m->step, m->stream));
   m->step += 1;
   MTRY(lbm::launch_mlp_adam(m->gpart, lbm::mlp_blocks(B), m->lpart, m->master, m->m, m->v, m->Wb, nullptr,
                             m->loss, m->step, lr, 1.0 / (3.0 * (double)B), m->stream));
@@ -148,7 +170,8 @@ lbm_status lbm_mlp_train_step(lbm_mlp* m, const float* x, const float* t, const 
 lbm_status lbm_mlp_gradient(lbm_mlp* m, const float* x, const float* t, int64_t B, float* grad, double* loss) {
   if (!m || !x || !t || !grad || B < 1 || B > kMaxBatch)
     return lbm::set_error(LBM_ERR_INVALID_ARG, "bad gradient arguments");
-  MTRY(lbm::launch_mlp_train(x, t, nullptr, (int)B, m->Wb, m->master, m->gpart, m->lpart, m->stream));
+  MTRY(lbm::launch_mlp_train(x, t, nullptr, (int)B, m->Wb, m->master, m->use_norm ? m->norm : nullptr, m->gpart,
+                              m->lpart, 0.0f, 0, m->stream));
   MTRY(lbm::launch_mlp_adam(m->gpart, lbm::mlp_blocks(B), m->lpart, m->master, m->m, m->v, m->Wb, m->grad,
                             m->loss, 0, 0.0f, 1.0 / (3.0 * (double)B), m->stream));
   MTRY(hipStreamSynchronize(m->stream));

@@ -117,16 +117,17 @@ constexpr int kMlpBf16 = 48 * 64 + 64 * 64 + 64 * 16;  // padded bfloat16 weight
 constexpr int kClosureNorm = 75;                      // mean[36], 1/std[36], out scale[3]
 int mlp_blocks(int64_t B);
 hipError_t launch_mlp_train(const float* X, const float* T, const int* idx, int B, const uint16_t* Wb,
-                            const float* master, float* gpart, double* lpart, hipStream_t s);
+                            const float* master, const float* norm, float* gpart, double* lpart, float noise,
+                            uint64_t key, hipStream_t s);
 hipError_t launch_mlp_adam(const float* gpart, int nblk, const double* lpart, float* master, float* m, float* v,
                            uint16_t* Wb, float* grad_out, double* loss_out, int step, float lr,
                            double inv_count, hipStream_t s);
-hipError_t launch_mlp_forward(const float* X, int M, const uint16_t* Wb, const float* master, float* Y,
-                              hipStream_t s);
+hipError_t launch_mlp_forward(const float* X, int M, const uint16_t* Wb, const float* master, const float* norm,
+                              float* Y, hipStream_t s);
 hipError_t launch_sample_boundary(const float* A, const Geometry& g, int ox, int oy, int wnx, int wny,
                                   const int* nodes, int n, float* feat, float* target, hipStream_t s);
 hipError_t launch_closure(const float* A, const Geometry& g, const uint16_t* Wb, const float* master,
-                          const float* norm, float* resid, hipStream_t s);
+                          const float* norm, int mask, float beta, int taper, float* resid, hipStream_t s);
 hipError_t launch_column_moments(const float* X, int64_t M, int ncols, double* out, hipStream_t s);
 
 // device weights of an lbm_mlp (lbm_closure_api.cpp)
