@@ -22,6 +22,9 @@ _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liblbm_oracle.so")
 
 WALL_FREE_SLIP, WALL_PERIODIC, WALL_NEBB, WALL_MOVING_BB = 0, 1, 2, 3
+BGK, MRT = 0, 1
+# Relaxation rates of the paper's MRT (Sec. 2.1); the last two (shear) are 1/tau.
+PAPER_S = (1.0, 1.1, 1.1, 1.0, 1.1, 1.0, 1.1, 0.0, 0.0)
 OUTLET_COPY_ALL, OUTLET_COPY_UNKNOWN = 0, 1
 
 
@@ -54,6 +57,8 @@ class _Params(ctypes.Structure):
         ("perturb_amp", ctypes.c_double),
         ("gx", ctypes.c_double),
         ("gy", ctypes.c_double),
+        ("collision", ctypes.c_int),
+        ("s_rates", ctypes.c_double * 9),
     ]
 
 
@@ -85,6 +90,8 @@ def _load():
     lib.oracle_tau.argtypes = [P]
     lib.oracle_tau.restype = ctypes.c_double
     lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_mrt_matrix.argtypes = [dp]
+    lib.oracle_mrt_meq.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
     _lib = lib
     return lib
 
@@ -109,6 +116,8 @@ class OracleParams:
     perturb_amp: float = 1e-3
     gx: float = 0.0
     gy: float = 0.0
+    collision: int = BGK
+    s_rates: tuple = PAPER_S
 
     def _c(self) -> _Params:
         d = self.diameter
@@ -119,6 +128,7 @@ class OracleParams:
             self.u_in, self.re, self.tau, self.wall,
             self.u_wall_top, self.u_wall_bottom, self.outlet_mode,
             1 if self.x_periodic else 0, self.perturb_amp, self.gx, self.gy,
+            self.collision, (ctypes.c_double * 9)(*self.s_rates),
         )
 
 
@@ -132,6 +142,18 @@ def digitise(p: OracleParams) -> np.ndarray:
     out = np.zeros((p.ny, p.nx), dtype=np.uint8)
     cp = p._c()
     lib.oracle_digitise(ctypes.byref(cp), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    return out
+
+
+def mrt_matrix() -> np.ndarray:
+    out = np.empty((9, 9))
+    _load().oracle_mrt_matrix(_dp(out))
+    return out
+
+
+def mrt_meq(rho, ux, uy) -> np.ndarray:
+    out = np.empty(9)
+    _load().oracle_mrt_meq(rho, ux, uy, _dp(out))
     return out
 
 

@@ -35,6 +35,64 @@ static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
 enum { R = 0, E = 1, N = 2, Wd = 3, S = 4, NE = 5, NW = 6, SW = 7, SE = 8 };
 
+/* Eq. 6: the transformation matrix M to the moments
+ * (rho, e, epsilon, j_x, q_x, j_y, q_y, p_xx, p_xy), columns in Table 1 order. */
+static const double MRT_M[9][9] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},          {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+    {4, -2, -2, -2, -2, 1, 1, 1, 1},      {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, -2, 0, 2, 0, 1, -1, -1, 1},       {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, -2, 0, 2, 1, 1, -1, -1},       {0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1}};
+
+void oracle_mrt_matrix(double* M) {
+  for (int i = 0; i < 9; ++i)
+    for (int j = 0; j < 9; ++j) M[i * 9 + j] = MRT_M[i][j];
+}
+
+/* The equilibrium moments of Sec. 2.1, read with the factor rho that makes
+ * them the moments of the equilibrium of Eq. 3 (the printed list omits it). */
+void oracle_mrt_meq(double rho, double ux, double uy, double* m) {
+  double uu = ux * ux + uy * uy;
+  m[0] = rho;
+  m[1] = rho * (-2.0 + 3.0 * uu);
+  m[2] = rho * (1.0 - 3.0 * uu);
+  m[3] = rho * ux;
+  m[4] = -rho * ux;
+  m[5] = rho * uy;
+  m[6] = -rho * uy;
+  m[7] = rho * (ux * ux - uy * uy);
+  m[8] = rho * ux * uy;
+}
+
+/* M^{-1} by Gauss-Jordan elimination with partial pivoting (once). */
+static double MRT_MINV[9][9];
+static int mrt_ready = 0;
+static void mrt_invert(void) {
+  double a[9][18];
+  for (int i = 0; i < 9; ++i)
+    for (int j = 0; j < 18; ++j) a[i][j] = j < 9 ? MRT_M[i][j] : (j - 9 == i ? 1.0 : 0.0);
+  for (int c = 0; c < 9; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 9; ++r)
+      if (fabs(a[r][c]) > fabs(a[piv][c])) piv = r;
+    for (int j = 0; j < 18; ++j) {
+      double t = a[c][j];
+      a[c][j] = a[piv][j];
+      a[piv][j] = t;
+    }
+    double d = a[c][c];
+    for (int j = 0; j < 18; ++j) a[c][j] /= d;
+    for (int r = 0; r < 9; ++r) {
+      if (r == c) continue;
+      double f = a[r][c];
+      for (int j = 0; j < 18; ++j) a[r][j] -= f * a[c][j];
+    }
+  }
+  for (int i = 0; i < 9; ++i)
+    for (int j = 0; j < 9; ++j) MRT_MINV[i][j] = a[i][j + 9];
+  mrt_ready = 1;
+}
+
 struct oracle {
   oracle_params p;
   int nx, ny;
@@ -47,6 +105,7 @@ struct oracle {
   double* rho_t;        /* density of f(t) per node, used by Eq. 11 */
   int state_is_post;    /* 1: f holds f*(t) (set by oracle_set_fstar) */
   long t;
+  double s[9];          /* MRT relaxation rates */
   /* fluid-to-solid links (node, direction) in row-major node order, fixed at
    * creation; the force sum of Eq. 14 runs over them in this order */
   long n_links;
@@ -96,6 +155,8 @@ static int build_links(oracle* o);
 
 oracle* oracle_create(const oracle_params* p, const unsigned char* solid) {
   if (!p || p->nx < 3 || p->ny < 3) return NULL;
+  /* the body force is a BGK-only test device (Guo forcing in the BGK form) */
+  if (p->collision == ORACLE_MRT && (p->gx != 0.0 || p->gy != 0.0)) return NULL;
   oracle* o = (oracle*)calloc(1, sizeof(oracle));
   if (!o) return NULL;
   o->p = *p;
@@ -104,6 +165,10 @@ oracle* oracle_create(const oracle_params* p, const unsigned char* solid) {
   o->tau = oracle_tau(p);
   o->u_top = isnan(p->u_wall_top) ? p->u_in : p->u_wall_top;
   o->u_bot = isnan(p->u_wall_bottom) ? p->u_in : p->u_wall_bottom;
+  for (int i = 0; i < 9; ++i) o->s[i] = p->s_rates[i];
+  if (!(o->s[7] > 0)) o->s[7] = 1.0 / o->tau;
+  if (!(o->s[8] > 0)) o->s[8] = 1.0 / o->tau;
+  if (!mrt_ready) mrt_invert();
   size_t nn = (size_t)o->nx * o->ny;
   o->solid = (unsigned char*)malloc(nn);
   o->f = (double*)malloc(nn * 9 * sizeof(double));
@@ -177,6 +242,22 @@ static int collide(oracle* o) {
       if (!(rho > 0.0 && rho < 10.0)) bad = 1;
       if (o->state_is_post) {
         for (int k = 0; k < 9; ++k) out[k] = fn[k];
+        continue;
+      }
+      if (o->p.collision == ORACLE_MRT) {
+        /* Eq. 6: f* = f - M^{-1} S M (f - f_eq), with M f_eq = m_eq */
+        double m[9], meq[9], dm[9];
+        for (int i = 0; i < 9; ++i) {
+          m[i] = 0.0;
+          for (int k = 0; k < 9; ++k) m[i] += MRT_M[i][k] * fn[k];
+        }
+        oracle_mrt_meq(rho, ux, uy, meq);
+        for (int i = 0; i < 9; ++i) dm[i] = o->s[i] * (m[i] - meq[i]);
+        for (int k = 0; k < 9; ++k) {
+          double acc = 0.0;
+          for (int i = 0; i < 9; ++i) acc += MRT_MINV[k][i] * dm[i];
+          out[k] = fn[k] - acc;
+        }
         continue;
       }
       for (int k = 0; k < 9; ++k) {

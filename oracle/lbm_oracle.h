@@ -35,6 +35,8 @@ enum {
 
 enum { ORACLE_OUTLET_COPY_ALL = 0, ORACLE_OUTLET_COPY_UNKNOWN = 1 };
 
+enum { ORACLE_BGK = 0, ORACLE_MRT = 1 };
+
 typedef struct {
   int nx, ny;             /* lattice nodes x in [0,nx), y in [0,ny) */
   int diameter;           /* cylinder diameter in lattice units; 0 = no cylinder */
@@ -49,6 +51,8 @@ typedef struct {
   int x_periodic;         /* 1 = periodic in x, no inlet/outlet (test boxes) */
   double perturb_amp;     /* initial v = amp*U*sin(2 pi y/(ny-1)) */
   double gx, gy;          /* body-force acceleration (Guo forcing), test boxes only */
+  int collision;          /* ORACLE_BGK (Eq. 2) or ORACLE_MRT (Eq. 6) */
+  double s_rates[9];      /* MRT relaxation rates diag(S); entries 7 and 8 <= 0 mean 1/tau */
 } oracle_params;
 
 typedef struct oracle oracle;
@@ -86,6 +90,11 @@ void oracle_get_f(const oracle* o, double* out);
 void oracle_set_f(oracle* o, const double* in);
 void oracle_get_fstar(const oracle* o, double* out);
 void oracle_set_fstar(oracle* o, const double* in);
+
+/* The MRT transformation matrix of Sec. 2.1 (row-major 9 x 9) and the
+ * moment-space equilibrium m_eq(rho, u, v) the oracle uses, for tests. */
+void oracle_mrt_matrix(double* M);
+void oracle_mrt_meq(double rho, double ux, double uy, double* meq);
 
 /* OpenMP threads the oracle's parallel loops use. */
 int oracle_threads(void);
