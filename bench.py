@@ -1,20 +1,23 @@
-"""Throughput benchmark of the D2Q9 BGK solver on one MI355X.
+"""Throughput benchmark of the D2Q9 solver on one MI355X.
 
 One step = one pass of the whole hot path over the lattice: pull streaming,
-half-way bounce-back on the cylinder, wall/outlet/inlet corrections, BGK
-collision and the FP64 momentum-exchange force (plus its fixed-order history
-reduction every 64 steps).  The default workload is the D = 160 cylinder
-channel (6560 x 3360 = 22.0 M nodes, Re = 100, U = 0.05, free-slip walls),
-whose two population buffers (1.6 GB) are far larger than the 256 MB
-Infinity Cache, so the step is bound by HBM bandwidth.
+half-way bounce-back on the cylinder, wall/outlet/inlet corrections, the
+collision (BGK by default) and the FP64 momentum-exchange force (plus its
+fixed-order history reduction every 64 steps).  The default workload is the
+D = 160 cylinder channel (6560 x 3360 = 22.0 M nodes, Re = 100, U = 0.05,
+free-slip walls), whose two population buffers (1.6 GB) are far larger than
+the 256 MB Infinity Cache.  At this size the library's default kernel takes
+two steps per launch with the intermediate populations in registers.
 
 Prints one JSON line:
   value      MLUPS = nx * ny * steps / time / 1e6 (all nodes)
   roofline   algorithmic bytes (72 B per node update: 9 FP32 loads + 9 FP32
-             stores) per step over the measured average step time, against
-             the 8 TB/s HBM3E peak; `traffic` comes from the committed
-             rocprofv3 FETCH_SIZE/WRITE_SIZE summary when it was taken on the
-             current kernel source, else null
+             stores) times the node updates of the timed region, over its
+             duration, against the 8 TB/s HBM3E peak; `traffic` is the HBM
+             bytes per launch from the committed rocprofv3 FETCH_SIZE /
+             WRITE_SIZE summary when it was taken on the current kernel
+             source and configuration (else null), and `hbm_GBs` the
+             bandwidth that traffic implies at the measured launch rate
   cpu_baseline  the FP64 oracle timed on this host on a bounded sample
 """
 from __future__ import annotations
@@ -39,16 +42,17 @@ def kernel_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def stored_traffic(workload: str):
-    """HBM bytes per step from the committed counter summary, if it was taken
-    on the current kernel source and workload."""
+def stored_traffic(workload: str, collision: str, variant: str):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source, workload, collision and variant."""
     try:
         d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if d.get("kernel_sha256_16") != kernel_hash() or d.get("workload") != workload:
+    if (d.get("kernel_sha256_16") != kernel_hash() or d.get("workload") != workload
+            or d.get("collision", "bgk") != collision or d.get("variant") != variant):
         return None
-    return d.get("bytes_per_step")
+    return d.get("bytes_per_launch")
 
 
 def copy_ceiling(torch, lbm, nbytes: int, reps: int = 20) -> float:
@@ -102,6 +106,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=400)
     ap.add_argument("--workload", default="cyl_d160")
     ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--collision", choices=("bgk", "mrt"), default="bgk",
+                    help="collision operator: BGK (Eq. 2) or MRT with the rates of Sec. 2.1 (Eq. 6)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-ceiling reference")
@@ -118,10 +124,14 @@ def main():
     import torch
 
     import paper_2605_02185_amd as lbm
-    from lbm_inputs import WORKLOADS
+    from lbm_inputs import PAPER_RATES, WORKLOADS
 
     torch.cuda.set_device(0)
     w = dict(WORKLOADS[args.workload])
+    if args.collision == "mrt":
+        w.update(collision=lbm.COLLISION_MRT, s_rates=PAPER_RATES)
+    else:
+        w = {k: v for k, v in w.items() if k not in ("collision", "s_rates")}
     p = lbm.make_params(**w)
     nodes = w["nx"] * w["ny"]
     stream = torch.cuda.current_stream()
@@ -147,8 +157,11 @@ def main():
     mlups = nodes * args.steps / (gpu_ms * 1e-3) / 1e6
     fluid = nodes - lbm.geometry(p)[1]
 
-    achieved = BYTES_PER_NODE * nodes / (ms_per_step * 1e-3) / 1e9
-    traffic = stored_traffic(args.workload)
+    vname = lbm.variant_name(lat.variant)
+    steps_per_launch = 2 if vname.startswith("t2_") else 1
+    launch_ms = ms_per_step * steps_per_launch
+    achieved = BYTES_PER_NODE * nodes * steps_per_launch / (launch_ms * 1e-3) / 1e9
+    traffic = stored_traffic(args.workload, args.collision, vname)
     roof = {
         "bound": "hbm",
         "achieved": round(achieved, 1),
@@ -156,8 +169,11 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / PEAK_HBM_GBS, 4),
         "traffic": traffic,
-        "algorithmic_bytes_per_step": BYTES_PER_NODE * nodes,
-        "kernel": "step_kernel",
+        "kernel": "step2_kernel" if steps_per_launch == 2 else "step_kernel",
+        "steps_per_launch": steps_per_launch,
+        "launch_us": round(launch_ms * 1e3, 2),
+        "algorithmic_bytes_per_launch": BYTES_PER_NODE * nodes * steps_per_launch,
+        "hbm_GBs": round(traffic / (launch_ms * 1e-3) / 1e9, 1) if traffic else None,
     }
     out = {
         "metric": "D2Q9 MLUPS & % HBM roofline",
@@ -176,7 +192,7 @@ def main():
             "workload": args.workload,
             "nx": w["nx"], "ny": w["ny"], "diameter": w["diameter"], "u_in": w["u_in"],
             "re": w["re"], "tau": round(lbm.tau_of(p), 6), "wall": "free-slip",
-            "outlet": "copy-all", "variant": lbm.variant_name(args.variant or 1),
+            "outlet": "copy-all", "collision": args.collision, "variant": vname,
             "graphs": not args.no_graphs,
         },
         "roofline": roof,

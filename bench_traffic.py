@@ -1,0 +1,87 @@
+"""Turns two rocprofv3 counter runs of bench.py (one with --pmc FETCH_SIZE,
+one with --pmc WRITE_SIZE, both with the copy reference enabled) into the
+HBM-traffic summary bench.py reports as roofline.traffic.
+
+Each counter is scaled by what it reads for the library's streaming copy of
+known size, run in the same process: FETCH_SIZE and WRITE_SIZE count in
+units that differ from bytes by a fixed factor on this chip.
+
+    python bench_traffic.py FETCH_CSV WRITE_CSV --variant t2_h4 [--workload cyl_d160] [--collision bgk]
+
+The variant is the one bench.py reports in config.variant for the same run.
+"""
+import argparse
+import csv
+import json
+import os
+import sys
+
+import bench
+from lbm_inputs import WORKLOADS
+
+
+def per_dispatch(path, counter, name_part):
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+            if r["Counter_Name"] == counter and name_part in r["Kernel_Name"]]
+    if not vals:
+        sys.exit(f"{path}: no {counter} rows for {name_part}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("fetch_csv")
+    ap.add_argument("write_csv")
+    ap.add_argument("--workload", default="cyl_d160")
+    ap.add_argument("--collision", default="bgk")
+    ap.add_argument("--variant", required=True)
+    a = ap.parse_args()
+    two = a.variant.startswith("t2_")
+    kname = "step2_kernel" if two else "step_kernel<"
+    w = WORKLOADS[a.workload]
+    nodes = w["nx"] * w["ny"]
+    copy_bytes = 9 * nodes * 4
+    copy_bytes -= copy_bytes % 16
+    f_step, n_f = per_dispatch(a.fetch_csv, "FETCH_SIZE", kname)
+    w_step, n_w = per_dispatch(a.write_csv, "WRITE_SIZE", kname)
+    f_copy, _ = per_dispatch(a.fetch_csv, "FETCH_SIZE", "copy_probe_kernel")
+    w_copy, _ = per_dispatch(a.write_csv, "WRITE_SIZE", "copy_probe_kernel")
+    fetch_scale = f_copy * 1024 / copy_bytes
+    write_scale = w_copy * 1024 / copy_bytes
+    read_b = f_step * 1024 / fetch_scale
+    write_b = w_step * 1024 / write_scale
+    steps = 2 if two else 1
+    alg = bench.BYTES_PER_NODE * nodes * steps
+    state = bench.BYTES_PER_NODE * nodes
+    out = {
+        "workload": a.workload,
+        "collision": a.collision,
+        "variant": a.variant,
+        "kernel": kname.rstrip("<"),
+        "steps_per_launch": steps,
+        "kernel_sha256_16": bench.kernel_hash(),
+        "dispatches": [n_f, n_w],
+        "bytes_per_launch": round(read_b + write_b),
+        "read_bytes": round(read_b),
+        "write_bytes": round(write_b),
+        # 72 B per node update, times the updates of one launch
+        "algorithmic_bytes_per_launch": alg,
+        # one read and one write of the nine populations of every node
+        "state_bytes_per_launch": state,
+        "ratio_to_state": round((read_b + write_b) / state, 4),
+        "ratio_to_algorithmic": round((read_b + write_b) / alg, 4),
+        "fetch_size_kib": round(f_step, 1),
+        "write_size_kib": round(w_step, 1),
+        "copy_probe_bytes_each_way": copy_bytes,
+        "copy_fetch_kib": round(f_copy, 1),
+        "copy_write_kib": round(w_copy, 1),
+        "fetch_scale": round(fetch_scale, 5),
+        "write_scale": round(write_scale, 5),
+    }
+    with open(bench.TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

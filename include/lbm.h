@@ -57,6 +57,12 @@ typedef enum {
   LBM_OUTLET_COPY_UNKNOWN = 1 /* only W, NW, SW; all nine at the two outlet corners */
 } lbm_outlet;
 
+/* Collision operator. */
+typedef enum {
+  LBM_COLLISION_BGK = 0, /* single relaxation time 1/tau (Eq. 2) */
+  LBM_COLLISION_MRT = 1  /* multiple relaxation times in moment space (Eq. 6, Sec. 2.1) */
+} lbm_collision;
+
 typedef struct {
   int32_t struct_size;   /* sizeof(lbm_params); set by lbm_params_init */
   int32_t nx, ny;        /* lattice size, both >= 3 */
@@ -70,18 +76,25 @@ typedef struct {
   double u_wall_top;     /* wall tangential velocity (NEBB, moving BB); NaN = u_in */
   double u_wall_bottom;  /* same for the bottom row; NaN = u_in */
   int32_t x_periodic;    /* 1: periodic in x, no inlet/outlet (test boxes) */
-  int32_t reserved0;
+  int32_t collision;     /* lbm_collision */
   double perturb_amp;    /* initial v = amp * U * sin(2 pi y/(ny-1)) */
   int64_t hist_capacity; /* force steps kept on the device (ring buffer) */
+  /* MRT only: diag(S) of Eq. 6 over the moments (rho, e, epsilon, j_x, q_x,
+   * j_y, q_y, p_xx, p_xy).  Entries 0, 3 and 5 belong to conserved moments
+   * and have no effect; entries 7 and 8 (the shear rates) <= 0 mean 1/tau,
+   * so that tau sets the viscosity through Eq. 5 as for BGK. */
+  double s_rates[9];
 } lbm_params;
 
 /* Defaults: D = 0, centre 21*D doubled (10.5 D), U = 0.1, Re = 100, tau
- * derived, free-slip walls, copy-all outlet, perturbation 1e-3, history of
- * 1<<20 steps.  nx and ny are set to 0 and must be filled in. */
+ * derived, free-slip walls, copy-all outlet, BGK, the rates of Sec. 2.1
+ * (1, 1.1, 1.1, 1, 1.1, 1, 1.1, 1/tau, 1/tau) for MRT, perturbation 1e-3,
+ * history of 1<<20 steps.  nx and ny are set to 0 and must be filled in. */
 void lbm_params_init(lbm_params* p);
 
 /* Host-only check of a parameter set (no GPU needed).  Rejects nx or ny < 3,
- * tau <= 1/2, U outside [0, 1/sqrt(3)), an unknown wall or outlet mode, a
+ * tau <= 1/2, U outside [0, 1/sqrt(3)), an unknown wall, outlet or collision
+ * mode, an MRT rate of a non-conserved moment outside (0, 2), a
  * cylinder with a solid node outside [3, nx-4] x [3, ny-4] (so that two fluid
  * nodes separate it from every edge row and column), and hist_capacity < 1. */
 lbm_status lbm_validate_params(const lbm_params* p);
@@ -109,7 +122,7 @@ void lbm_destroy(lbm_ctx* ctx);
 /* Advance n >= 0 time steps.  One step is, per node, the pull of the
  * post-collision populations of the neighbours (streaming, Eq. 2), half-way
  * bounce-back at the cylinder (Sec. 3.1), the boundary corrections of
- * Sec. 2.3 and the inlet, then the BGK collision (Eqs. 2-4); the force on the
+ * Sec. 2.3 and the inlet, then the collision (BGK, Eqs. 2-4, or MRT, Eq. 6); the force on the
  * cylinder is taken by momentum exchange (Eq. 14) in the same pass.
  * Stream-ordered and asynchronous; a divergence is reported by the next
  * lbm_sync / lbm_forces / lbm_fields / lbm_get_populations call. */
@@ -159,11 +172,18 @@ typedef struct {
 lbm_status lbm_shedding_stats(const double* cd, const double* cl, int64_t n, double d, double u,
                               int32_t periods, lbm_shedding* out);
 
-/* Kernel selection for measurement and autotuning: variant 0 = automatic.
- * Valid variants are 1..lbm_num_variants(); the result is bit-identical for
- * every variant. */
+/* Kernel selection for measurement and autotuning.  Valid variants are
+ * 1..lbm_num_variants(); variant 0 selects the context's default.  The result
+ * is bit-identical for every variant.  Variants named "t2_*" advance two time
+ * steps per launch and keep the intermediate populations f*(t+1) in
+ * registers, so one launch reads and writes each population once for two
+ * node updates; single steps (an odd remainder, or every step while a learned
+ * closure is enabled) then run the one-step kernel.  The default of a new
+ * context is the two-step "t2_h4" for lattices of 2^20 nodes or more and the
+ * one-step "v1_ty1_nt" below.  lbm_get_variant reports the variant in use. */
 int32_t lbm_num_variants(void);
 lbm_status lbm_set_variant(lbm_ctx* ctx, int32_t variant);
+int32_t lbm_get_variant(const lbm_ctx* ctx);
 const char* lbm_variant_name(int32_t variant);
 
 /* Step scheduling.  With graphs enabled (the default) lbm_step replays HIP

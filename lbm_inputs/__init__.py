@@ -10,6 +10,10 @@ each wall measured from the cylinder surface; Sec. 3.1 of the paper):
   cyl_d40  1640 x 840,  D = 40,  U = 0.05, Re = 100
   cyl_d80  3280 x 1680, D = 80,  U = 0.05, Re = 100
   cyl_d160 6560 x 3360, D = 160, U = 0.05, Re = 100
+The paper's own runs (Sec. 3.1), a 40 D x 20 D lattice with the centre 10 D
+from the inlet and (up to half a node) from both walls, MRT collision:
+  cyl_d20_mrt  800 x 400,  D = 20, U = 0.02, Re = 100, tau = 0.512
+  cyl_d40_mrt 1600 x 800,  D = 40, U = 0.02, Re = 100, tau = 0.524
   ensemble 64 cases, D uniform in 8..32, Re uniform in [60, 200], U = 0.05
   trunc_d40 1040 x 440 truncated window around a D = 40 cylinder
 """
@@ -36,11 +40,24 @@ def channel(d: int, u: float = 0.05, re: float = 100.0) -> dict:
     return dict(nx=41 * d, ny=21 * d, diameter=d, cx2=21 * d, cy2=21 * d, u_in=u, re=re)
 
 
+# diag(S) of Sec. 2.1; 0 in the two shear entries stands for 1/tau
+PAPER_RATES = (1.0, 1.1, 1.1, 1.0, 1.1, 1.0, 1.1, 0.0, 0.0)
+MRT = 1
+
+
+def paper_channel(d: int = 20, u: float = 0.02, re: float = 100.0) -> dict:
+    """The 40 D x 20 D lattice of Sec. 3.1 with the MRT collision."""
+    return dict(nx=40 * d, ny=20 * d, diameter=d, cx2=20 * d, cy2=20 * d, u_in=u, re=re,
+                collision=MRT, s_rates=PAPER_RATES)
+
+
 WORKLOADS = {
     "cyl_d10": dict(channel(10, u=0.1), tau=0.53),
     "cyl_d40": channel(40),
     "cyl_d80": channel(80),
     "cyl_d160": channel(160),
+    "cyl_d20_mrt": paper_channel(20),
+    "cyl_d40_mrt": paper_channel(40),
 }
 
 

@@ -13,6 +13,8 @@ import numpy as np
 
 from . import _lib
 from ._lib import (
+    COLLISION_BGK,
+    COLLISION_MRT,
     OUTLET_COPY_ALL,
     OUTLET_COPY_UNKNOWN,
     WALL_FREE_SLIP,
@@ -30,7 +32,7 @@ __all__ = [
     "Lattice", "Ensemble", "Mlp", "column_moments", "make_params", "MLP_PARAMS", "validate", "tau_of", "geometry", "shedding_stats", "copy_probe",
     "num_variants", "variant_name", "LbmError", "DivergedError", "RangeError",
     "WALL_FREE_SLIP", "WALL_PERIODIC", "WALL_NEBB", "WALL_MOVING_BB",
-    "OUTLET_COPY_ALL", "OUTLET_COPY_UNKNOWN",
+    "OUTLET_COPY_ALL", "OUTLET_COPY_UNKNOWN", "COLLISION_BGK", "COLLISION_MRT",
 ]
 
 
@@ -130,6 +132,11 @@ class Lattice:
 
     def set_variant(self, v: int):
         check(_lib.lib.lbm_set_variant(self._h, v))
+
+    @property
+    def variant(self) -> int:
+        """Kernel variant in use (1-based, see variant_name)."""
+        return _lib.lib.lbm_get_variant(self._h)
 
     def set_graphs(self, enable: bool):
         check(_lib.lib.lbm_set_graphs(self._h, 1 if enable else 0))

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 OK, ERR_INVALID_ARG, ERR_HIP, ERR_OOM, ERR_DIVERGED, ERR_RANGE, ERR_STATE = 0, -1, -2, -3, -4, -5, -6
 WALL_FREE_SLIP, WALL_PERIODIC, WALL_NEBB, WALL_MOVING_BB = 0, 1, 2, 3
 OUTLET_COPY_ALL, OUTLET_COPY_UNKNOWN = 0, 1
+COLLISION_BGK, COLLISION_MRT = 0, 1
 
 
 class LbmError(RuntimeError):
@@ -50,9 +51,10 @@ class Params(ctypes.Structure):
         ("u_wall_top", ctypes.c_double),
         ("u_wall_bottom", ctypes.c_double),
         ("x_periodic", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("collision", ctypes.c_int32),
         ("perturb_amp", ctypes.c_double),
         ("hist_capacity", ctypes.c_int64),
+        ("s_rates", ctypes.c_double * 9),
     ]
 
 
@@ -93,6 +95,7 @@ def _load():
         "lbm_shedding_stats": (i32, [dp, dp, i64, ctypes.c_double, ctypes.c_double, i32, ctypes.POINTER(Shedding)]),
         "lbm_num_variants": (i32, []),
         "lbm_set_variant": (i32, [vp, i32]),
+        "lbm_get_variant": (i32, [vp]),
         "lbm_variant_name": (ctypes.c_char_p, [i32]),
         "lbm_set_graphs": (i32, [vp, ctypes.c_int]),
         "lbm_copy_probe": (i32, [vp, vp, i64, vp]),
@@ -147,7 +150,9 @@ def check(status: int):
 def make_params(nx, ny, diameter=0, cx2=None, cy2=None, u_in=0.1, re=100.0, tau=0.0,
                 wall=WALL_FREE_SLIP, outlet_mode=OUTLET_COPY_ALL, u_wall_top=math.nan,
                 u_wall_bottom=math.nan, x_periodic=False, perturb_amp=1e-3,
-                hist_capacity=1 << 20) -> Params:
+                hist_capacity=1 << 20, collision=COLLISION_BGK, s_rates=None) -> Params:
+    """lbm_params from keywords; s_rates (9 values, MRT) defaults to the
+    rates of Sec. 2.1, with 0 for the shear rates meaning 1/tau."""
     p = Params()
     lib.lbm_params_init(ctypes.byref(p))
     p.nx, p.ny, p.diameter = nx, ny, diameter
@@ -159,4 +164,9 @@ def make_params(nx, ny, diameter=0, cx2=None, cy2=None, u_in=0.1, re=100.0, tau=
     p.x_periodic = 1 if x_periodic else 0
     p.perturb_amp = perturb_amp
     p.hist_capacity = hist_capacity
+    p.collision = collision
+    if s_rates is not None:
+        if len(s_rates) != 9:
+            raise ValueError("s_rates needs 9 values")
+        p.s_rates[:] = [float(v) for v in s_rates]
     return p

@@ -22,8 +22,8 @@ from ._lib import OUTLET_COPY_UNKNOWN, WALL_FREE_SLIP
 
 N_FEATURES = 36
 
-# Closed-loop settings that keep the learned walls stable (measured at D = 40,
-# see the design doc): training-input noise of one standard deviation, the two
+# Closed-loop settings that keep the learned walls stable (measured at D = 40):
+# training-input noise of one standard deviation, the two
 # rows only (the outlet keeps its extrapolation), rows plain within 2 D of the
 # inlet and outlet, and a low-pass of the applied residual.
 NOISE = 1.0

@@ -114,6 +114,14 @@ Physics make_physics(const lbm_params* p) {
   ph.wall = p->wall;
   ph.outlet_mode = p->outlet_mode;
   ph.x_periodic = p->x_periodic;
+  ph.mrt = p->collision == LBM_COLLISION_MRT;
+  auto rate = [&](int i) { return (float)(p->s_rates[i] > 0 ? p->s_rates[i] : 1.0 / lbm_params_tau(p)); };
+  ph.s_e = rate(1);
+  ph.s_eps = rate(2);
+  ph.s_qx = rate(4);
+  ph.s_qy = rate(6);
+  ph.s_pxx = rate(7);
+  ph.s_pxy = rate(8);
   return ph;
 }
 
@@ -142,6 +150,9 @@ struct lbm_ctx {
   uint16_t* d_flags = nullptr;
   int32_t* d_link_index = nullptr;
   double2* d_partials = nullptr;
+  // two-step variants: segments that need the boundary code (seg * ntx + strip)
+  int* d_gen = nullptr;
+  int n_gen = 0;
   double* d_hist = nullptr;
   int64_t* d_step = nullptr;
   int* d_bad = nullptr;
@@ -176,6 +187,9 @@ void lbm_params_init(lbm_params* p) {
   p->u_wall_bottom = NAN;
   p->perturb_amp = 1e-3;
   p->hist_capacity = 1 << 20;
+  p->collision = LBM_COLLISION_BGK;
+  const double paper_rates[9] = {1.0, 1.1, 1.1, 1.0, 1.1, 1.0, 1.1, 0.0, 0.0};  // Sec. 2.1
+  for (int i = 0; i < 9; ++i) p->s_rates[i] = paper_rates[i];
 }
 
 double lbm_params_tau(const lbm_params* p) {
@@ -196,6 +210,14 @@ lbm_status lbm_validate_params(const lbm_params* p) {
   if (p->outlet_mode != LBM_OUTLET_COPY_ALL && p->outlet_mode != LBM_OUTLET_COPY_UNKNOWN)
     return fail(LBM_ERR_INVALID_ARG, "unknown outlet mode %d", p->outlet_mode);
   if (p->x_periodic != 0 && p->x_periodic != 1) return fail(LBM_ERR_INVALID_ARG, "x_periodic must be 0 or 1");
+  if (p->collision != LBM_COLLISION_BGK && p->collision != LBM_COLLISION_MRT)
+    return fail(LBM_ERR_INVALID_ARG, "unknown collision %d", p->collision);
+  if (p->collision == LBM_COLLISION_MRT)
+    for (int i : {1, 2, 4, 6, 7, 8}) {
+      const double s = p->s_rates[i];
+      if ((i == 7 || i == 8) && s <= 0) continue;  // 1/tau
+      if (!(s > 0.0 && s < 2.0)) return fail(LBM_ERR_INVALID_ARG, "MRT rate s_rates[%d] = %g outside (0, 2)", i, s);
+    }
   if (!(p->u_in >= 0.0 && p->u_in < 1.0 / std::sqrt(3.0)))
     return fail(LBM_ERR_INVALID_ARG, "u_in = %g outside [0, 1/sqrt(3))", p->u_in);
   if (p->tau <= 0 && !(p->re > 0)) return fail(LBM_ERR_INVALID_ARG, "re must be > 0 when tau is derived");
@@ -243,6 +265,8 @@ lbm_status lbm_geometry(const lbm_params* p, uint8_t* solid_mask, int64_t* n_sol
 
 int32_t lbm_num_variants(void) { return lbm::num_variants(); }
 
+int32_t lbm_get_variant(const lbm_ctx* c) { return c ? c->variant : 0; }
+
 const char* lbm_variant_name(int32_t v) {
   if (v < 1 || v > lbm::num_variants()) return "";
   return lbm::variant(v).name;
@@ -254,9 +278,28 @@ const char* lbm_last_error(void) { return g_err.c_str(); }
 
 namespace {
 
-void set_tiling(lbm_ctx* c, int v) {
-  lbm::tiling_for_variant(c->geo, v, &c->tiling);
+lbm_status set_tiling(lbm_ctx* c, int v) {
+  lbm::Tiling t;
+  lbm::tiling_for_variant(c->geo, v, &t);
+  if (lbm::variant(v).steps == 2) {
+    std::vector<int> gen;
+    for (int seg = 0; seg < t.nty; ++seg)
+      for (int strip = 0; strip < t.ntx; ++strip)
+        if (!lbm::interior_segment(c->geo, t, c->p.x_periodic != 0, strip, seg)) gen.push_back(seg * t.ntx + strip);
+    int* d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(int) * gen.size()));
+    const hipError_t e = hipMemcpy(d, gen.data(), sizeof(int) * gen.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return fail(LBM_ERR_HIP, "hipMemcpy: %s", hipGetErrorString(e));
+    }
+    (void)hipFree(c->d_gen);
+    c->d_gen = d;
+    c->n_gen = (int)gen.size();
+  }
+  c->tiling = t;
   c->variant = v;
+  return LBM_OK;
 }
 
 // force contributions per step: one per link node, at least one row entry
@@ -288,6 +331,7 @@ void free_ctx(lbm_ctx* c) {
   (void)hipFree(c->d_flags);
   (void)hipFree(c->d_link_index);
   (void)hipFree(c->d_partials);
+  (void)hipFree(c->d_gen);
   (void)hipFree(c->d_hist);
   (void)hipFree(c->d_step);
   (void)hipFree(c->d_bad);
@@ -334,7 +378,10 @@ lbm_status lbm_create(const lbm_params* p, void* stream, lbm_ctx** out) {
   const std::vector<int32_t>& link_index = hg.link_index;
   c->phys = lbm::make_physics(p);
 
-  set_tiling(c, 1);
+  if ((st = set_tiling(c, lbm::default_variant((int64_t)p->nx * p->ny))) != LBM_OK) {
+    free_ctx(c);
+    return st;
+  }
 
 #define CREATE_TRY(call)            \
   do {                              \
@@ -387,22 +434,29 @@ void lbm_destroy(lbm_ctx* ctx) { free_ctx(ctx); }
 
 lbm_status lbm_set_variant(lbm_ctx* c, int32_t v) {
   if (check_ctx(c)) return LBM_ERR_INVALID_ARG;
-  if (v == 0) v = 1;
+  if (v == 0) v = lbm::default_variant((int64_t)c->p.nx * c->p.ny);
   if (v < 1 || v > lbm::num_variants()) return fail(LBM_ERR_INVALID_ARG, "variant %d out of range", v);
   lbm_status st = flush(c);
   if (st != LBM_OK) return st;
   drop_graphs(c);
-  set_tiling(c, v);
-  return LBM_OK;
+  return set_tiling(c, v);
 }
 
 }  // extern "C"
 
 namespace {
 
-// Enqueues one step on stream s (buffers by c->cur, ring slot c->pending) and
-// advances the host-side bookkeeping; folds the ring when it is full.
-lbm_status enqueue_step(lbm_ctx* c, hipStream_t s) {
+// Two steps fit in one launch when the variant takes two, the learned closure
+// (which needs the state before every step) is off and the ring has room.
+bool pairable(const lbm_ctx* c) {
+  return lbm::variant(c->variant).steps == 2 && !c->mlp && c->pending + 2 <= lbm::kRing;
+}
+
+// Enqueues k = 1 or 2 steps (k = 2 only when pairable) on stream s, buffers by
+// c->cur and ring slots from c->pending, and advances the host-side
+// bookkeeping; folds the ring when it is full.  One launch always moves the
+// state from buf[cur] to buf[cur ^ 1].
+lbm_status enqueue_step(lbm_ctx* c, hipStream_t s, int k = 1) {
   lbm::StepArgs a{};
   a.g = c->geo;
   a.p = c->phys;
@@ -412,16 +466,26 @@ lbm_status enqueue_step(lbm_ctx* c, hipStream_t s) {
   a.B = c->buf[c->cur ^ 1];
   a.slot = c->pending;
   a.partial = c->d_partials + (size_t)c->pending * slots_of(c);
+  int v = c->variant;
+  if (k == 2) {
+    a.partial2 = a.partial + slots_of(c);
+    a.gen = c->d_gen;
+    a.n_gen = c->n_gen;
+  } else if (lbm::variant(v).steps != 1) {
+    v = 1;  // a single step of a two-step variant: the plain one-step kernel
+    lbm::tiling_for_variant(c->geo, v, &a.t);
+  }
   if (c->mlp) {
     const lbm::MlpDevice md = lbm::mlp_device(c->mlp);
     HIP_TRY(lbm::launch_closure(a.A, c->geo, md.Wb, md.master, c->d_norm, c->closure_mask, c->closure_beta,
                                 c->closure_taper, c->d_resid, s));
     a.closure = c->d_resid;
   }
-  HIP_TRY(lbm::launch_step(a, c->variant, s));
+  HIP_TRY(lbm::launch_step(a, v, s));
   c->cur ^= 1;
-  c->step += 1;
-  if (++c->pending == lbm::kRing) {
+  c->step += k;
+  c->pending += k;
+  if (c->pending == lbm::kRing) {
     HIP_TRY(lbm::launch_force_reduce(c->d_partials, slots_of(c), c->pending, c->d_hist,
                                      c->p.hist_capacity, c->d_step, c->d_bad, c->d_bad_step, s));
     c->pending = 0;
@@ -436,7 +500,11 @@ lbm_status capture(lbm_ctx* c) {
   const int64_t step0 = c->step;
   HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
   lbm_status st = LBM_OK;
-  for (int i = 0; i < lbm::kRing && st == LBM_OK; ++i) st = enqueue_step(c, c->capture_stream);
+  for (int i = 0; i < lbm::kRing && st == LBM_OK;) {
+    const int k = pairable(c) ? 2 : 1;
+    st = enqueue_step(c, c->capture_stream, k);
+    i += k;
+  }
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
   c->cur = cur0;  // capturing ran nothing
@@ -596,9 +664,10 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   int64_t i = 0;
   // plain launches until the ring is empty, then whole graphs
   while (i < n && c->pending != 0) {
-    lbm_status st = enqueue_step(c, c->stream);
+    const int k = n - i >= 2 && pairable(c) ? 2 : 1;
+    lbm_status st = enqueue_step(c, c->stream, k);
     if (st != LBM_OK) return st;
-    ++i;
+    i += k;
   }
   if (c->use_graphs) {
     while (n - i >= lbm::kRing) {
@@ -607,14 +676,17 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
         if (st != LBM_OK) return st;
       }
       HIP_TRY(hipGraphLaunch(c->graph[c->cur], c->stream));
-      // kRing is even: the state returns to the same buffer
+      // kRing steps take an even number of launches (kRing one-step ones or
+      // kRing/2 two-step ones): the state returns to the same buffer
       c->step += lbm::kRing;
       i += lbm::kRing;
     }
   }
-  for (; i < n; ++i) {
-    lbm_status st = enqueue_step(c, c->stream);
+  while (i < n) {
+    const int k = n - i >= 2 && pairable(c) ? 2 : 1;
+    lbm_status st = enqueue_step(c, c->stream, k);
     if (st != LBM_OK) return st;
+    i += k;
   }
   return flush(c);
 }

@@ -109,7 +109,8 @@ std::string tune_key(const lbm_batch* b) {
   std::string k = "batch";
   for (const auto& p : b->params) {
     char buf[96];
-    snprintf(buf, sizeof buf, ":%dx%d/d%d/w%d/x%d", p.nx, p.ny, p.diameter, p.wall, p.x_periodic);
+    snprintf(buf, sizeof buf, ":%dx%d/d%d/w%d/x%d/c%d", p.nx, p.ny, p.diameter, p.wall, p.x_periodic,
+             p.collision);
     k += buf;
   }
   // keep keys short and stable: FNV-1a of the full description
@@ -120,6 +121,13 @@ std::string tune_key(const lbm_batch* b) {
   return out;
 }
 
+// The ensemble launch walks its flattened tile list in order, one step per
+// launch: variants with a remapped tile order or two steps per launch are
+// for single lattices only.
+bool batch_capable(int v) {
+  return v >= 1 && v <= lbm::num_variants() && !lbm::variant(v).remap_xcd && lbm::variant(v).steps == 1;
+}
+
 int cache_lookup(const char* path, const std::string& key) {
   if (!path) return 0;
   FILE* f = fopen(path, "r");
@@ -127,7 +135,7 @@ int cache_lookup(const char* path, const std::string& key) {
   char k[256];
   int v = 0, found = 0;
   while (fscanf(f, "%255s %d", k, &v) == 2)
-    if (key == k && v >= 1 && v <= lbm::num_variants()) found = v;
+    if (key == k && batch_capable(v)) found = v;
   fclose(f);
   return found;
 }
@@ -285,7 +293,7 @@ lbm_status lbm_batch_create(const lbm_params* cases, const int64_t* budgets, int
       lbm_status s2 = create_impl(cases, nullptr, n, stream, &scratch);
       double tbest = 1e30;
       for (int v = 1; s2 == LBM_OK && v <= lbm::num_variants(); ++v) {
-        if (lbm::variant(v).remap_xcd) continue;
+        if (!batch_capable(v)) continue;
         const double t = time_variant(scratch, v, 20);
         if (t < tbest) {
           tbest = t;

@@ -45,6 +45,8 @@ struct Physics {
   float u_in;      // inlet velocity
   float u_top, u_bot;
   int wall, outlet_mode, x_periodic;
+  int mrt;         // 1: Eq. 6 with the rates below instead of Eq. 2
+  float s_e, s_eps, s_qx, s_qy, s_pxx, s_pxy;  // rates of the non-conserved moments
 };
 
 // Tiling of one launch.  A tile is tile_x consecutive nodes of tile_y
@@ -52,8 +54,30 @@ struct Physics {
 struct Tiling {
   int tile_x, tile_y;
   int ntx, nty;          // tiles along x and y
-  int remap_xcd;         // 1: give each XCD a contiguous range of tiles
+  int remap_xcd;         // block-to-tile map: 0 plain, 1 XCD bands, 2 XCD-interleaved rows
 };
+
+// Two steps per launch: each wave owns kStrip2 output columns (its 64 lanes
+// hold one more column on either side) of one segment of tile_y rows.
+// Without x-periodicity the strips are aligned to the right edge.
+constexpr int kStrip2 = 62;
+constexpr int kSub2 = 2;  // rows per wave where a segment needs boundary code
+
+__host__ __device__ inline int strip_start(const Geometry& g, const Tiling& t, bool x_periodic, int strip) {
+  return x_periodic ? strip * kStrip2 : g.nx - kStrip2 * (t.ntx - strip);
+}
+
+// A segment is interior when it has the full tile_y rows and every node its
+// wave updates in the first step (columns xs-1 .. xs+62, rows y0-1 .. y0+H)
+// is plain bulk fluid: away from the edges and outside the cylinder's flag
+// rectangle.  The others need the boundary code.
+__host__ __device__ inline bool interior_segment(const Geometry& g, const Tiling& t, bool x_periodic, int strip,
+                                                 int seg) {
+  const int xs = strip_start(g, t, x_periodic, strip), y0 = seg * t.tile_y;
+  const int xa = xs - 1, xb = xs + kStrip2, ya = y0 - 1, yb = y0 + t.tile_y;
+  if (xa < 1 || xb > g.nx - 2 || ya < 1 || yb > g.ny - 2) return false;
+  return !(xa < g.rx0 + g.rw && xb >= g.rx0 && ya < g.ry0 + g.rh && yb >= g.ry0);
+}
 
 struct StepArgs {
   const float* __restrict__ A;  // post-collision populations f*(t), 9 planes
@@ -62,6 +86,9 @@ struct StepArgs {
   Physics p;
   Tiling t;
   double2* partial;             // this step's force contributions [n_link_nodes]
+  double2* partial2;            // the second step's, for kernels that take two steps
+  const int* gen;               // two-step launches: segments (seg * ntx + strip) that are not interior
+  int n_gen;
   const float* closure;         // learned-closure residuals [boundary node][3], or null
   int* bad;                     // watchdog: min ring slot with a bad density
   int slot;                     // ring slot of this step
@@ -84,14 +111,17 @@ struct CaseArgs {
 
 struct Variant {
   const char* name;
-  int tile_x, tile_y;  // nodes along x (= 256 * vx) and rows per tile
+  int tile_x, tile_y;  // nodes along x (= 256 * vx) and rows per tile; for two-step
+                       // variants the output columns per wave and rows per segment
   int vx;              // consecutive nodes per lane on the bulk path
   int remap_xcd, nontemporal;
+  int steps;           // time steps per launch (1, or 2 with the intermediate state in registers)
 };
 
 // Kernel launchers (lbm_kernels.hip).  All return the launch status.
 int num_variants();
 const Variant& variant(int v);  // 1-based
+int default_variant(int64_t nodes);
 hipError_t launch_step(const StepArgs& a, int v, hipStream_t s);
 hipError_t launch_step_batch(const CaseArgs* cases, const int2* tiles, int ntiles, int cur, int slot,
                              int partial_stride, int v, hipStream_t s);

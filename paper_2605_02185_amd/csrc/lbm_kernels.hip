@@ -1,4 +1,4 @@
-// gfx950 kernels of the D2Q9 BGK cylinder-flow solver (arXiv 2605.02185).
+// gfx950 kernels of the D2Q9 lattice Boltzmann cylinder-flow solver (arXiv 2605.02185).
 //
 // State between steps: post-collision populations f*(x, t) in 9 SoA planes,
 // rows padded to a multiple of 64 floats, stored shifted by the rest
@@ -13,7 +13,8 @@
 //   2. boundary corrections of the populations missing at the edges
 //      (Sec. 2.3: free-slip Eq. 7, periodic Eq. 8, NEBB Eqs. 9-10, moving-wall
 //      bounce-back Eq. 11; outlet Eq. 13; Zou-He velocity inlet, Sec. 3.1)
-//   3. moments (Eq. 4), equilibrium (Eq. 3), BGK relaxation (Eq. 2)
+//   3. moments (Eq. 4), equilibrium (Eq. 3), BGK relaxation (Eq. 2) or the
+//      multiple-relaxation-time collision of Eq. 6
 // The paper's order is collide -> stream -> correct; pulling the previous
 // step's post-collision values and colliding at the end of the same pass is
 // the same sequence shifted by half a step, with one read and one write of
@@ -25,6 +26,7 @@
 #include "lbm_internal.h"
 
 #include <climits>
+#include <cstring>
 
 namespace lbm {
 namespace {
@@ -42,15 +44,10 @@ constexpr float W0 = 4.0f / 9.0f, W1 = 1.0f / 9.0f, W2 = 1.0f / 36.0f;
 // Flags a density that is non-finite or outside (0, 10).  Contraction is
 // off and every fused multiply-add is written out, so that each kernel
 // variant (scalar or vector bulk path, general path) rounds identically.
-__device__ __forceinline__ void collide(const float (&g)[9], float omega, float (&out)[9], bool& bad) {
+__device__ __forceinline__ void collide_bgk(const float (&g)[9], float drho, float rho, float ux, float uy,
+                                            float omega, float (&out)[9]) {
 #pragma clang fp contract(off)
-  const float drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
-  const float rho = 1.0f + drho;
-  const float ir = 1.0f / rho;
-  const float ux = (((g[1] - g[3]) + (g[5] - g[7])) + (g[8] - g[6])) * ir;
-  const float uy = (((g[2] - g[4]) + (g[5] - g[7])) + (g[6] - g[8])) * ir;
   const float usq = 1.5f * __fmaf_rn(ux, ux, uy * uy);
-  bad |= !(rho > 0.0f && rho < 10.0f);
   float cu[9];
   cu[0] = 0.0f;
   cu[1] = ux;
@@ -70,6 +67,68 @@ __device__ __forceinline__ void collide(const float (&g)[9], float omega, float 
   }
 }
 
+// Eq. 6: f* = f - M^-1 S (M f - m_eq), on the deviations g.  The rows of M
+// are orthogonal, M M^T = D = diag(9, 36, 36, 6, 12, 6, 12, 4, 4), so
+// M^-1 = M^T D^-1 and the correction of population k is
+//   sum_i M_ik a_i,   a_i = s_i (m_i - m_eq,i) / D_i,
+// over the six non-conserved moments (rho, j_x, j_y are unchanged because
+// their equilibria equal them).  The rest state's moments M w are
+// (1, -2, 1, 0, ...), so m - m_eq is formed from the moments of g and
+// drho, j without cancellation of O(1) terms:
+//   e:   M_e g + 2 drho - 3 rho u.u      eps: M_eps g - drho + 3 rho u.u
+//   q_x: M_qx g + j_x                    q_y: M_qy g + j_y
+//   p_xx: M_pxx g - rho (u_x^2 - u_y^2)  p_xy: M_pxy g - rho u_x u_y
+// with m_eq = rho (-2 + 3 u.u, 1 - 3 u.u, u_x, -u_x, u_y, -u_y,
+// u_x^2 - u_y^2, u_x u_y), the equilibrium moments of Eq. 3.
+__device__ __forceinline__ void collide_mrt(const float (&g)[9], float drho, float rho, float ux, float uy,
+                                            float jx, float jy, const Physics& p, float (&out)[9]) {
+#pragma clang fp contract(off)
+  const float s14 = (g[1] + g[2]) + (g[3] + g[4]);
+  const float s58 = (g[5] + g[6]) + (g[7] + g[8]);
+  const float ru2 = rho * __fmaf_rn(ux, ux, uy * uy);
+  const float me = __fmaf_rn(2.0f, s58, __fmaf_rn(-4.0f, g[0], -s14));
+  const float meps = __fmaf_rn(-2.0f, s14, __fmaf_rn(4.0f, g[0], s58));
+  const float mqx = __fmaf_rn(-2.0f, g[1] - g[3], (g[5] - g[6]) + (g[8] - g[7]));
+  const float mqy = __fmaf_rn(-2.0f, g[2] - g[4], (g[5] + g[6]) - (g[7] + g[8]));
+  const float mpxx = (g[1] + g[3]) - (g[2] + g[4]);
+  const float mpxy = (g[5] - g[6]) + (g[7] - g[8]);
+  const float a1 = p.s_e * (1.0f / 36.0f) * __fmaf_rn(-3.0f, ru2, __fmaf_rn(2.0f, drho, me));
+  const float a2 = p.s_eps * (1.0f / 36.0f) * __fmaf_rn(3.0f, ru2, meps - drho);
+  const float a4 = p.s_qx * (1.0f / 12.0f) * (mqx + jx);
+  const float a6 = p.s_qy * (1.0f / 12.0f) * (mqy + jy);
+  const float a7 = p.s_pxx * 0.25f * __fmaf_rn(-rho, __fmaf_rn(ux, ux, -(uy * uy)), mpxx);
+  const float a8 = p.s_pxy * 0.25f * __fmaf_rn(-rho, ux * uy, mpxy);
+  // columns of M: rest (1,-4,4,...), axis k (1,-1,-2, c_x, -2c_x, c_y, -2c_y,
+  // c_x^2-c_y^2, 0), diagonal k (1,2,1, c_x, c_x, c_y, c_y, 0, c_x c_y)
+  const float axis = __fmaf_rn(2.0f, a2, a1);
+  const float diag = __fmaf_rn(2.0f, a1, a2);
+  out[0] = __fmaf_rn(4.0f, a1 - a2, g[0]);
+  out[1] = g[1] + (__fmaf_rn(2.0f, a4, axis) - a7);
+  out[2] = g[2] + (__fmaf_rn(2.0f, a6, axis) + a7);
+  out[3] = g[3] + (__fmaf_rn(-2.0f, a4, axis) - a7);
+  out[4] = g[4] + (__fmaf_rn(-2.0f, a6, axis) + a7);
+  out[5] = g[5] - ((diag + a8) + (a4 + a6));
+  out[6] = g[6] - ((diag - a8) + (a6 - a4));
+  out[7] = g[7] - ((diag + a8) - (a4 + a6));
+  out[8] = g[8] - ((diag - a8) + (a4 - a6));
+}
+
+__device__ __forceinline__ void collide(const float (&g)[9], const Physics& p, float (&out)[9], bool& bad) {
+#pragma clang fp contract(off)
+  const float drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+  const float rho = 1.0f + drho;
+  const float ir = 1.0f / rho;
+  const float jx = ((g[1] - g[3]) + (g[5] - g[7])) + (g[8] - g[6]);
+  const float jy = ((g[2] - g[4]) + (g[5] - g[7])) + (g[6] - g[8]);
+  const float ux = jx * ir;
+  const float uy = jy * ir;
+  bad |= !(rho > 0.0f && rho < 10.0f);
+  if (p.mrt)
+    collide_mrt(g, drho, rho, ux, uy, jx, jy, p, out);
+  else
+    collide_bgk(g, drho, rho, ux, uy, p.omega, out);
+}
+
 template <bool NT>
 __device__ __forceinline__ void store9(float* __restrict__ B, uint32_t plane, uint32_t o, const float (&v)[9]) {
 #pragma unroll
@@ -80,14 +139,6 @@ __device__ __forceinline__ void store9(float* __restrict__ B, uint32_t plane, ui
     else
       *dst = v[k];
   }
-}
-
-template <bool NT>
-__device__ __forceinline__ void collide_store(const float (&g)[9], float omega, float* __restrict__ B,
-                                              uint32_t plane, uint32_t o, bool& bad) {
-  float out[9];
-  collide(g, omega, out, bad);
-  store9<NT>(B, plane, o, out);
 }
 
 __device__ __forceinline__ uint16_t node_flags(const Geometry& g, int x, int y) {
@@ -124,10 +175,11 @@ __device__ __forceinline__ void pull(const StepArgs& a, int x, int y, uint16_t f
   }
 }
 
-// Top (y = ny-1) or bottom (y = 0) row correction at node (x, y).
-__device__ __forceinline__ void wall_bc(const StepArgs& a, int x, int y, float (&g)[9]) {
-  const bool top = y == a.g.ny - 1;
-  switch (a.p.wall) {
+// Top (y = ny-1) or bottom (y = 0) row correction of the streamed
+// populations g of one node; fs are the node's own post-collision
+// populations f*(t), read only by the moving-wall treatment.
+__device__ __forceinline__ void wall_bc(const Physics& p, bool top, const float (&fs)[9], float (&g)[9]) {
+  switch (p.wall) {
     case kWallFreeSlip:  // Eq. 7: specular reflection at the node
       if (top) {
         g[4] = g[2];
@@ -140,7 +192,7 @@ __device__ __forceinline__ void wall_bc(const StepArgs& a, int x, int y, float (
       }
       break;
     case kWallNebb: {  // Eqs. 9-10: wall density from the known populations
-      const float U = top ? a.p.u_top : a.p.u_bot;
+      const float U = top ? p.u_top : p.u_bot;
       const float d13 = 0.5f * (g[1] - g[3]);
       if (top) {
         const float rw = 1.0f + ((g[0] + g[1] + g[3]) + 2.0f * (g[2] + g[5] + g[6]));
@@ -158,10 +210,7 @@ __device__ __forceinline__ void wall_bc(const StepArgs& a, int x, int y, float (
       break;
     }
     case kWallMovingBB: {  // Eq. 11 with the node's own f* and density
-      const float U = top ? a.p.u_top : a.p.u_bot;
-      float fs[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) fs[k] = load(a.A, a.g, k, x, y);
+      const float U = top ? p.u_top : p.u_bot;
       const float rho = 1.0f + (((fs[0] + fs[1]) + (fs[2] + fs[3])) + ((fs[4] + fs[5]) + (fs[6] + fs[7])) + fs[8]);
       const float m = rho * U * (1.0f / 6.0f);
       if (top) {
@@ -180,6 +229,44 @@ __device__ __forceinline__ void wall_bc(const StepArgs& a, int x, int y, float (
   }
 }
 
+// Zou-He velocity inlet, u = (U, 0), on the streamed populations of an inlet
+// node; the two inlet corners are equilibrium nodes at rho = 1, u = (U, 0).
+__device__ __forceinline__ void inlet_bc(const Physics& p, bool corner, float (&g)[9]) {
+  const float U = p.u_in;
+  if (corner) {
+    const float usq = 1.5f * U * U;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const float w = k == 0 ? W0 : (k < 5 ? W1 : W2);
+      const float cu = (float)CX[k] * U;
+      g[k] = w * (cu * (3.0f + 4.5f * cu) - usq);
+    }
+  } else {  // the known weights sum to 1
+    const float rho = (1.0f + ((g[0] + g[2]) + g[4] + 2.0f * ((g[3] + g[6]) + g[7]))) / (1.0f - U);
+    const float d24 = 0.5f * (g[2] - g[4]);
+    g[1] = g[3] + (2.0f / 3.0f) * rho * U;
+    g[5] = g[7] - d24 + rho * U * (1.0f / 6.0f);
+    g[8] = g[6] + d24 + rho * U * (1.0f / 6.0f);
+  }
+}
+
+// Eq. 14: each bounced population g_k = f*_opp(k)(x) left along c_opp(k)
+// and came back along c_k, giving the body 2 c_opp(k) f*_opp(k).  Written to
+// the node's fixed slot of this step's contributions.
+__device__ __forceinline__ void link_force(const Geometry& geo, double2* __restrict__ partial, int x, int y,
+                                           uint16_t fl, const float (&g)[9]) {
+  double Fx = 0.0, Fy = 0.0;
+#pragma unroll
+  for (int k = 1; k < 9; ++k)
+    if ((fl >> k) & 1) {
+      const double fk = (double)g[k] + (k < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+      Fx -= 2.0 * (double)CX[k] * fk;
+      Fy -= 2.0 * (double)CY[k] * fk;
+    }
+  const int idx = geo.link_index[(y - geo.ry0) * geo.rw + (x - geo.rx0)];
+  partial[idx] = make_double2(Fx, Fy);
+}
+
 // Streamed and row-corrected populations of node (x, y).  With a learned
 // closure the network's residuals are added to the wall treatment's values
 // of the three missing populations (top row nodes 0 .. nx-3, bottom row
@@ -189,7 +276,12 @@ __device__ __forceinline__ void gather(const StepArgs& a, int x, int y, uint16_t
   const bool wall_row = a.p.wall != kWallPeriodic && (y == 0 || y == a.g.ny - 1);
   const bool wall_x = a.p.x_periodic || (x >= 1 && x <= a.g.nx - 2);
   if (wall_row && wall_x) {
-    wall_bc(a, x, y, g);
+    float fs[9];
+    if (a.p.wall == kWallMovingBB) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) fs[k] = load(a.A, a.g, k, x, y);
+    }
+    wall_bc(a.p, y == a.g.ny - 1, fs, g);
     if (a.closure) {
       if (y == a.g.ny - 1) {
         const float* r = a.closure + 3 * (x - 1);
@@ -206,18 +298,19 @@ __device__ __forceinline__ void gather(const StepArgs& a, int x, int y, uint16_t
   }
 }
 
-template <bool NT>
-__device__ __forceinline__ void general_node(const StepArgs& a, int x, int y, bool& bad) {
+// Post-collision populations f*(t+1) of a node that is not plain bulk
+// fluid: pull, boundary corrections, force contributions (written when
+// `owner`), collision.  Solid nodes keep their (never streamed) values.
+__device__ __forceinline__ void general_update(const StepArgs& a, int x, int y, bool owner, float (&out)[9],
+                                               bool& bad) {
   const int nx = a.g.nx, ny = a.g.ny;
-  const uint32_t o = (uint32_t)y * (uint32_t)a.g.pitch + (uint32_t)x;
-  const uint32_t P = (uint32_t)a.g.plane;
   const bool open_x = !a.p.x_periodic;
   const bool outlet = open_x && x == nx - 1;
   const bool corner_y = a.p.wall != kWallPeriodic && (y == 0 || y == ny - 1);
   const uint16_t fl = node_flags(a.g, x, y);
-  if (fl & kSolid) {  // solid nodes keep their (never streamed) values
+  if (fl & kSolid) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) a.B[k * P + o] = a.A[k * P + o];
+    for (int k = 0; k < 9; ++k) out[k] = load(a.A, a.g, k, x, y);
     return;
   }
   float g[9];
@@ -243,43 +336,19 @@ __device__ __forceinline__ void general_node(const StepArgs& a, int x, int y, bo
   } else {
     gather(a, x, y, fl, g);
   }
-  if (open_x && x == 0) {
-    const float U = a.p.u_in;
-    if (corner_y) {  // inlet corners: equilibrium at rho = 1, u = (U, 0)
-      const float usq = 1.5f * U * U;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        const float w = k == 0 ? W0 : (k < 5 ? W1 : W2);
-        const float cu = (float)CX[k] * U;
-        g[k] = w * (cu * (3.0f + 4.5f * cu) - usq);
-      }
-    } else {  // Zou-He velocity inlet, u = (U, 0); the known weights sum to 1
-      const float rho = (1.0f + ((g[0] + g[2]) + g[4] + 2.0f * ((g[3] + g[6]) + g[7]))) / (1.0f - U);
-      const float d24 = 0.5f * (g[2] - g[4]);
-      g[1] = g[3] + (2.0f / 3.0f) * rho * U;
-      g[5] = g[7] - d24 + rho * U * (1.0f / 6.0f);
-      g[8] = g[6] + d24 + rho * U * (1.0f / 6.0f);
-    }
-  }
-  if (fl >> 1) {
-    // Eq. 14: each bounced population g_k = f*_opp(k)(x) left along c_opp(k)
-    // and came back along c_k, giving the body 2 c_opp(k) f*_opp(k).
-    double Fx = 0.0, Fy = 0.0;
-#pragma unroll
-    for (int k = 1; k < 9; ++k)
-      if ((fl >> k) & 1) {
-        const double fk = (double)g[k] + (k < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
-        Fx -= 2.0 * (double)CX[k] * fk;
-        Fy -= 2.0 * (double)CY[k] * fk;
-      }
-    const int idx = a.g.link_index[(y - a.g.ry0) * a.g.rw + (x - a.g.rx0)];
-    a.partial[idx] = make_double2(Fx, Fy);
-  }
-  collide_store<NT>(g, a.p.omega, a.B, P, o, bad);
+  if (open_x && x == 0) inlet_bc(a.p, corner_y, g);
+  if ((fl >> 1) && owner) link_force(a.g, a.partial, x, y, fl, g);
+  collide(g, a.p, out, bad);
 }
 
 template <bool NT>
-__device__ __forceinline__ void bulk_node(const StepArgs& a, int x, int y, bool& bad) {
+__device__ __forceinline__ void general_node(const StepArgs& a, int x, int y, bool& bad) {
+  float out[9];
+  general_update(a, x, y, true, out, bad);
+  store9<NT>(a.B, (uint32_t)a.g.plane, (uint32_t)y * (uint32_t)a.g.pitch + (uint32_t)x, out);
+}
+
+__device__ __forceinline__ void bulk_update(const StepArgs& a, int x, int y, float (&out)[9], bool& bad) {
   const float* __restrict__ A = a.A;
   const uint32_t P = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
   const uint32_t o = (uint32_t)y * Wp + (uint32_t)x;
@@ -293,7 +362,14 @@ __device__ __forceinline__ void bulk_node(const StepArgs& a, int x, int y, bool&
   g[6] = A[6 * P + o - Wp + 1];
   g[7] = A[7 * P + o + Wp + 1];
   g[8] = A[8 * P + o + Wp - 1];
-  collide_store<NT>(g, a.p.omega, a.B, P, o, bad);
+  collide(g, a.p, out, bad);
+}
+
+template <bool NT>
+__device__ __forceinline__ void bulk_node(const StepArgs& a, int x, int y, bool& bad) {
+  float out[9];
+  bulk_update(a, x, y, out, bad);
+  store9<NT>(a.B, (uint32_t)a.g.plane, (uint32_t)y * (uint32_t)a.g.pitch + (uint32_t)x, out);
 }
 
 template <int VX>
@@ -355,7 +431,7 @@ __device__ __forceinline__ void bulk_vec(const StepArgs& a, int x0, int y, bool&
     g[3] = j == VX - 1 ? w_in : w[j < VX - 1 ? j + 1 : 0];
     g[6] = j == VX - 1 ? nw_in : nw[j < VX - 1 ? j + 1 : 0];
     g[7] = j == VX - 1 ? sw_in : sw[j < VX - 1 ? j + 1 : 0];
-    collide(g, a.p.omega, f, bad);
+    collide(g, a.p, f, bad);
 #pragma unroll
     for (int k = 0; k < 9; ++k) out[k][j] = f[k];
   }
@@ -369,13 +445,26 @@ __device__ __forceinline__ void bulk_vec(const StepArgs& a, int x0, int y, bool&
   }
 }
 
-// Blocks are dispatched round-robin over the 8 XCDs (block id mod 8); hand
-// each XCD a contiguous range of tiles so that neighbouring tiles, which
-// share halo cache lines, meet in the same L2.
+// Blocks are dispatched round-robin over the 8 XCDs (block id mod 8), and
+// each XCD has its own L2.  Two block-to-tile maps keep neighbouring tiles of
+// a row, which share the halo cache lines of the x-shifted planes, on one XCD:
+//  1: each XCD gets a contiguous range of tiles (a band of rows);
+//  2: XCD i gets the tile rows congruent to i mod 8, in row order, so all
+//     eight still sweep the lattice together (one narrow band of rows at any
+//     time, as with the plain order) and a row's tiles meet in one L2.
+// Tile rows past the last complete group of eight keep the plain order.
 __device__ __forceinline__ int remap_xcd(int id, int n) {
   const int xcd = id & 7, local = id >> 3;
   const int per = n >> 3, rem = n & 7;
   return xcd * per + min(xcd, rem) + local;
+}
+
+__device__ __forceinline__ int remap_xcd_rows(int id, int ntx, int nty) {
+  const int full = (nty >> 3) * ntx * 8;
+  if (id >= full) return id;
+  const int xcd = id & 7, local = id >> 3;
+  const int r = local / ntx, t = local - r * ntx;
+  return (8 * r + xcd) * ntx + t;
 }
 
 // One tile = tile_x = 256 * VX consecutive nodes of TY rows; lane t of the
@@ -409,8 +498,290 @@ __device__ __forceinline__ void process_tile(const StepArgs& a, int bx, int by) 
 template <int TY, int VX, bool NT>
 __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
   const int ntiles = a.t.ntx * a.t.nty;
-  const int tile = a.t.remap_xcd ? remap_xcd((int)blockIdx.x, ntiles) : (int)blockIdx.x;
+  const int id = (int)blockIdx.x;
+  const int tile = a.t.remap_xcd == 1   ? remap_xcd(id, ntiles)
+                   : a.t.remap_xcd == 2 ? remap_xcd_rows(id, a.t.ntx, a.t.nty)
+                                        : id;
   process_tile<TY, VX, NT>(a, tile % a.t.ntx, tile / a.t.ntx);
+}
+
+// ---------------------------------------------------------------------------
+// Two time steps per launch, the intermediate state kept in registers.
+//
+// Each wave owns a strip of kStrip2 = 62 output columns and a segment of
+// tile_y output rows; its 64 lanes hold the columns from one left of the strip
+// to one right of it.  The wave walks its segment down in y.  At row r it
+// computes f*(t+1) from memory for all 64 lanes and keeps it; the rows r-2,
+// r-1 and r of f*(t+1) then give f*(t+2) at row r-1, pulled from registers
+// (the x-neighbours by cross-lane moves), and only that is written.  One
+// launch thus reads and writes each population once for two node updates.
+// The edge lanes and the rows just outside the segment are computed by two
+// waves, but each node's output, force contribution and density check come
+// from its owner only.  Every node sees the same FP32 values and the same
+// arithmetic as in two one-step launches, so the results are equal bit for
+// bit.
+//
+// Segments whose first-step nodes are all plain bulk fluid (interior_segment)
+// run a lean, fully unrolled path (bulk_wave); the others run the boundary
+// code of the one-step kernel on registers (general_wave, first_update,
+// second_update).  Without x-periodicity the strips are aligned to the right
+// edge, so the outlet column is always lane 62 and the column it copies
+// (nx-2) lane 61.
+// Value of the lane below (lane l gets lane l-1) and above (lane l gets
+// l+1), by DPP whole-wave shifts (a VALU move, no LDS permute).  The lane at
+// the wave's end keeps its own value; only halo lanes read it.
+__device__ __forceinline__ float from_left(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_right(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+// The nine pulled values of a bulk node at (x, y) clamped into the interior,
+// so that the addresses are valid for every lane; used only where the node
+// turns out to be bulk fluid.
+__device__ __forceinline__ void prefetch_bulk(const StepArgs& a, int x, int y, float (&v)[9]) {
+  const int cx = min(max(x, 1), a.g.nx - 2), cy = min(max(y, 1), a.g.ny - 2);
+  const float* __restrict__ A = a.A;
+  const uint32_t P = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
+  const uint32_t o = (uint32_t)cy * Wp + (uint32_t)cx;
+  v[0] = A[o];
+  v[1] = A[P + o - 1];
+  v[2] = A[2 * P + o - Wp];
+  v[3] = A[3 * P + o + 1];
+  v[4] = A[4 * P + o + Wp];
+  v[5] = A[5 * P + o - Wp - 1];
+  v[6] = A[6 * P + o - Wp + 1];
+  v[7] = A[7 * P + o + Wp + 1];
+  v[8] = A[8 * P + o + Wp - 1];
+}
+
+// f*(t+1) at (x, y) for one lane; `active` false gives zeros (outside the
+// lattice), `owner` selects who records forces and density failures.
+__device__ __forceinline__ void first_update(const StepArgs& a, int x, int y, bool active, bool owner,
+                                             const float (&pre)[9], float (&out)[9], bool& bad) {
+  const int nx = a.g.nx, ny = a.g.ny;
+  const bool special = active && (x == 0 || x >= nx - 1 || y == 0 || y == ny - 1 || in_rect(a.g, x, y));
+  bool b = false;
+  if (__any(special)) {
+    if (active) general_update(a, x, y, owner, out, b);
+  } else if (active) {
+    collide(pre, a.p, out, b);  // the bulk pull, loaded ahead
+  }
+  if (!active) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) out[k] = 0.0f;
+  }
+  bad |= b && owner;
+}
+
+// f*(t+2) at (x, y) from f*(t+1) of rows y-1 (w0), y (w1) and y+1 (w2) of
+// this lane's column and its two neighbour lanes.  The same steps as
+// general_update, with the pulled values taken from registers.
+__device__ __forceinline__ void second_update(const StepArgs& a, int x, int y, bool active, bool owner,
+                                              const float (&w0)[9], const float (&w1)[9], const float (&w2)[9],
+                                              float (&out)[9], bool& bad) {
+  const int nx = a.g.nx, ny = a.g.ny;
+  // f*_k(x - c_k, y - c_k,y): row by c_y, the lane to the left for c_x = +1
+  float c[9];
+  c[0] = w1[0];
+  c[1] = from_left(w1[1]);
+  c[2] = w0[2];
+  c[3] = from_right(w1[3]);
+  c[4] = w2[4];
+  c[5] = from_left(w0[5]);
+  c[6] = from_right(w0[6]);
+  c[7] = from_right(w2[7]);
+  c[8] = from_left(w2[8]);
+  const bool special = active && (x == 0 || x >= nx - 1 || y == 0 || y == ny - 1 || in_rect(a.g, x, y));
+  bool b = false;
+  if (!__any(special)) {
+    if (active) collide(c, a.p, out, b);
+    bad |= b && owner;
+    return;
+  }
+  const bool open_x = !a.p.x_periodic;
+  const bool outlet = active && open_x && x == nx - 1;
+  const bool corner_y = a.p.wall != kWallPeriodic && (y == 0 || y == ny - 1);
+  const uint16_t fl = active ? node_flags(a.g, x, y) : 0;
+  float g[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    if (k > 0 && ((fl >> k) & 1)) {  // half-way bounce-back on the cylinder
+      g[k] = w1[OPP[k]];
+      continue;
+    }
+    int sx = x - CX[k], sy = y - CY[k];
+    if (a.p.x_periodic) sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+    if (a.p.wall == kWallPeriodic) sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+    g[k] = (sx >= 0 && sx < nx && sy >= 0 && sy < ny) ? c[k] : 0.0f;
+  }
+  const bool wall_row = a.p.wall != kWallPeriodic && (y == 0 || y == ny - 1);
+  const bool wall_x = a.p.x_periodic || (x >= 1 && x <= nx - 2);
+  if (active && wall_row && wall_x) wall_bc(a.p, y == ny - 1, w1, g);
+  // Eq. 13: the corrected populations of x = nx-2 are the left lane's g
+  if (__any(outlet)) {
+    float G[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) G[k] = from_left(g[k]);
+    if (outlet) {
+      if (a.p.outlet_mode == kOutletCopyUnknown && !corner_y) {
+        g[3] = G[3];
+        g[6] = G[6];
+        g[7] = G[7];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) g[k] = G[k];
+      }
+    }
+  }
+  if (!active) return;
+  if (fl & kSolid) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) out[k] = w1[k];
+    return;
+  }
+  if (open_x && x == 0) inlet_bc(a.p, corner_y, g);
+  if ((fl >> 1) && owner) link_force(a.g, a.partial2, x, y, fl, g);
+  collide(g, a.p, out, b);
+  bad |= b && owner;
+}
+
+// The nine pulled values of bulk node (x, y).
+__device__ __forceinline__ void load_pull(const StepArgs& a, int x, int y, float (&v)[9]) {
+  const float* __restrict__ A = a.A;
+  const uint32_t P = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
+  const uint32_t o = (uint32_t)y * Wp + (uint32_t)x;
+  v[0] = A[o];
+  v[1] = A[P + o - 1];
+  v[2] = A[2 * P + o - Wp];
+  v[3] = A[3 * P + o + 1];
+  v[4] = A[4 * P + o + Wp];
+  v[5] = A[5 * P + o - Wp - 1];
+  v[6] = A[6 * P + o - Wp + 1];
+  v[7] = A[7 * P + o + Wp + 1];
+  v[8] = A[8 * P + o + Wp - 1];
+}
+
+// Interior waves, H = tile_y rows.  The row loop is unrolled; its loads run
+// two rows ahead, and the H output rows stay in registers until every load
+// of the wave has been issued, so no load waits behind a store (on this chip
+// one counter tracks both, and a wait for a load also waits for the older
+// stores).
+template <bool NT, int H>
+__device__ __forceinline__ void bulk_wave(const StepArgs& a, int strip, int seg) {
+  const int lane = (int)(threadIdx.x & 63);
+  if (!interior_segment(a.g, a.t, a.p.x_periodic, strip, seg)) return;
+  const int xs = strip_start(a.g, a.t, a.p.x_periodic, strip);
+  const int y0 = seg * H;
+  const int x = xs - 1 + lane;
+  const bool out_col = lane >= 1 && lane <= kStrip2;
+  float w[3][9], pre[3][9], out[H][9];
+  load_pull(a, x, y0 - 1, pre[0]);
+  load_pull(a, x, y0, pre[1]);
+  bool bad1 = false, bad2 = false;
+#pragma unroll
+  for (int i = 0; i < H + 2; ++i) {  // f*(t+1) of row y0-1+i
+    if (i + 2 < H + 2) load_pull(a, x, y0 + 1 + i, pre[(i + 2) % 3]);
+    bool b1 = false;
+    collide(pre[i % 3], a.p, w[i % 3], b1);
+    if (i >= 1 && i <= H) bad1 |= b1;
+    if (i >= 2) {  // f*(t+2) of row y0+i-2
+      const float(&wa)[9] = w[(i + 1) % 3];
+      const float(&wb)[9] = w[(i + 2) % 3];
+      const float(&wc)[9] = w[i % 3];
+      float c[9];
+      c[0] = wb[0];
+      c[1] = from_left(wb[1]);
+      c[2] = wa[2];
+      c[3] = from_right(wb[3]);
+      c[4] = wc[4];
+      c[5] = from_left(wa[5]);
+      c[6] = from_right(wa[6]);
+      c[7] = from_right(wc[7]);
+      c[8] = from_left(wc[8]);
+      collide(c, a.p, out[i - 2], bad2);
+    }
+  }
+  if (!out_col) return;
+  const uint32_t P = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
+#pragma unroll
+  for (int j = 0; j < H; ++j) store9<NT>(a.B, P, (uint32_t)(y0 + j) * Wp + (uint32_t)x, out[j]);
+  if (bad1) atomicMin(a.bad, a.slot);
+  if (bad2) atomicMin(a.bad, a.slot + 1);
+}
+
+// kSub2 rows of a segment that is not interior, with the boundary code.
+template <bool NT>
+__device__ __forceinline__ void general_wave(const StepArgs& a, int segment, int sub) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int S = a.t.ntx, H = a.t.tile_y;
+  const int strip = segment % S, seg = segment / S;
+  const int nx = a.g.nx, ny = a.g.ny;
+  const bool xper = a.p.x_periodic, yper = a.p.wall == kWallPeriodic;
+  const int xs = strip_start(a.g, a.t, xper, strip);
+  const int y0 = seg * H + sub * kSub2;
+  if (y0 >= ny) return;
+  const int y1 = min(y0 + kSub2, ny);
+  const int ux = xs - 1 + lane;  // column before wrapping
+  const int x = xper ? ((ux % nx) + nx) % nx : ux;
+  const bool col_ok = xper || (ux >= 0 && ux < nx);
+  const bool out_col = lane >= 1 && lane <= kStrip2 && ux >= 0 && ux < nx;
+  const uint32_t P = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
+  float w0[9], w1[9], w2[9], pre[9], pre1[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) w0[k] = w1[k] = w2[k] = 0.0f;
+  auto row_of = [&](int r) { return yper ? (r < 0 ? r + ny : (r >= ny ? r - ny : r)) : r; };
+  prefetch_bulk(a, x, row_of(y0 - 1), pre);
+  prefetch_bulk(a, x, row_of(y0), pre1);
+  bool bad1 = false, bad2 = false;
+  for (int r = y0 - 1; r <= y1; ++r) {
+    float nxt[9];
+    prefetch_bulk(a, x, row_of(r + 2), nxt);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      w0[k] = w1[k];
+      w1[k] = w2[k];
+    }
+    const bool row_ok = yper || (r >= 0 && r < ny);
+    const int y = row_of(r);
+    first_update(a, x, y, col_ok && row_ok, out_col && r >= y0 && r < y1, pre, w2, bad1);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      pre[k] = pre1[k];
+      pre1[k] = nxt[k];
+    }
+    if (r > y0) {
+      const int y2 = r - 1;
+      float out[9];
+      second_update(a, x, y2, col_ok, out_col, w0, w1, w2, out, bad2);
+      if (out_col) store9<NT>(a.B, P, (uint32_t)y2 * Wp + (uint32_t)x, out);
+    }
+  }
+  if (bad1) atomicMin(a.bad, a.slot);
+  if (bad2) atomicMin(a.bad, a.slot + 1);
+}
+
+// One launch, two steps.  The first blocks take the boundary sub-segments
+// (listed on the host, kSub2 rows each, so that they are many and short and
+// run alongside the interior ones); the later ones one segment per wave, in
+// row-major order of (segment, strip), so that the waves in flight at any
+// time cover a narrow band of rows, four neighbouring strips per block.
+// (Orders that keep vertically adjacent segments on one XCD, so that their
+// shared rows are read once into its L2, fetch 30 % fewer bytes but ran
+// 4-10 % slower: the plain order's DRAM locality wins.)
+template <bool NT, int H>
+__global__ __launch_bounds__(256) void step2_kernel(StepArgs a) {
+  constexpr int per = H / kSub2;
+  const int gen_blocks = (a.n_gen * per + 3) / 4;
+  const int b = (int)blockIdx.x, w = (int)(threadIdx.x >> 6);
+  if (b < gen_blocks) {
+    const int wave = b * 4 + w;
+    if (wave < a.n_gen * per) general_wave<NT>(a, a.gen[wave / per], wave % per);
+    return;
+  }
+  const int wave = (b - gen_blocks) * 4 + w;
+  if (wave < a.t.ntx * a.t.nty) bulk_wave<NT, H>(a, wave % a.t.ntx, wave / a.t.ntx);
 }
 
 // One step of a whole ensemble: block b processes tile tiles[b] = (case,
@@ -423,7 +794,7 @@ __global__ __launch_bounds__(256) void step_batch_kernel(const CaseArgs* __restr
                                                          int slot, int partial_stride) {
   const int2 ct = tiles[blockIdx.x];
   const CaseArgs& c = cases[ct.x];
-  StepArgs a;
+  StepArgs a{};  // every field not set below (closure, second-step slots) is null
   a.A = c.buf[cur];
   a.B = c.buf[cur ^ 1];
   a.g = c.g;
@@ -584,20 +955,35 @@ __global__ __launch_bounds__(256) void copy_probe_kernel(const float4v* __restri
 }
 
 constexpr Variant kVariants[] = {
-    // name              tile_x tile_y vx remap nt
-    {"v1_ty1_nt", 256, 1, 1, 0, 1},
-    {"v1_ty1_xcd_nt", 256, 1, 1, 1, 1},
-    {"v1_ty1", 256, 1, 1, 0, 0},
-    {"v1_ty2_nt", 256, 2, 1, 0, 1},
-    {"v2_ty1_nt", 512, 1, 2, 0, 1},
-    {"v4_ty1_nt", 1024, 1, 4, 0, 1},
-    {"v4_ty1_xcd_nt", 1024, 1, 4, 1, 1},
+    // name              tile_x tile_y vx remap nt steps
+    {"v1_ty1_nt", 256, 1, 1, 0, 1, 1},
+    {"v1_ty1_xcd_nt", 256, 1, 1, 1, 1, 1},
+    {"v1_ty1", 256, 1, 1, 0, 0, 1},
+    {"v1_ty2_nt", 256, 2, 1, 0, 1, 1},
+    {"v2_ty1_nt", 512, 1, 2, 0, 1, 1},
+    {"v4_ty1_nt", 1024, 1, 4, 0, 1, 1},
+    {"v4_ty1_xcd_nt", 1024, 1, 4, 1, 1, 1},
+    {"v1_ty1_xrow_nt", 256, 1, 1, 2, 1, 1},
+    {"v2_ty1_xrow_nt", 512, 1, 2, 2, 1, 1},
+    {"t2_h4", kStrip2, 4, 1, 0, 0, 2},
+    {"t2_h8", kStrip2, 8, 1, 0, 0, 2},
+    {"t2_h8_nt", kStrip2, 8, 1, 0, 1, 2},
+    {"t2_h16", kStrip2, 16, 1, 0, 0, 2},
 };
 
 }  // namespace
 
 int num_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 const Variant& variant(int v) { return kVariants[v - 1]; }
+
+// The two-step kernel pays once the interior segments fill the chip (measured
+// faster from 1.4 M nodes on, slower at 86 k); the one-step kernel below.
+int default_variant(int64_t nodes) {
+  if (nodes >= ((int64_t)1 << 20))
+    for (int v = 1; v <= num_variants(); ++v)
+      if (std::strcmp(kVariants[v - 1].name, "t2_h4") == 0) return v;
+  return 1;
+}
 
 hipError_t launch_step_batch(const CaseArgs* cases, const int2* tiles, int ntiles, int cur, int slot,
                              int partial_stride, int v, hipStream_t s) {
@@ -629,6 +1015,21 @@ hipError_t launch_force_reduce_batch(const CaseArgs* cases, int ncases, int coun
 
 hipError_t launch_step(const StepArgs& a, int v, hipStream_t s) {
   const Variant& var = variant(v);
+  if (var.steps == 2) {
+    const int blocks = (a.n_gen * (var.tile_y / kSub2) + 3) / 4 + (a.t.ntx * a.t.nty + 3) / 4;
+    const dim3 grid((unsigned)blocks), block(256);
+#define LBM_T2(NT, H)                                                      \
+  if (var.nontemporal == NT && var.tile_y == H) {                          \
+    hipLaunchKernelGGL((step2_kernel<NT, H>), grid, block, 0, s, a);       \
+    return hipGetLastError();                                              \
+  }
+    LBM_T2(false, 4)
+    LBM_T2(false, 8)
+    LBM_T2(true, 8)
+    LBM_T2(false, 16)
+#undef LBM_T2
+    return hipErrorInvalidValue;
+  }
   const dim3 grid((unsigned)(a.t.ntx * a.t.nty)), block(256);
 #define LBM_CASE(TY, VX, NT)                                                       \
   if (var.tile_y == TY && var.vx == VX && var.nontemporal == NT) {                  \

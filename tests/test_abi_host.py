@@ -61,6 +61,11 @@ def test_params_defaults_and_tau():
         dict(hist_capacity=0),
         dict(diameter=-1),
         dict(perturb_amp=math.inf),
+        dict(collision=2),
+        dict(collision=_lib.COLLISION_MRT, s_rates=(1, 2.0, 1.1, 1, 1.1, 1, 1.1, 0, 0)),
+        dict(collision=_lib.COLLISION_MRT, s_rates=(1, 1.1, 1.1, 1, 0.0, 1, 1.1, 0, 0)),
+        dict(collision=_lib.COLLISION_MRT, s_rates=(1, 1.1, 1.1, 1, 1.1, 1, 1.1, 2.5, 0)),
+        dict(collision=_lib.COLLISION_MRT, s_rates=(1, 1.1, 1.1, 1, 1.1, 1, math.nan, 0, 0)),
     ],
 )
 def test_validation_rejects(change):
@@ -71,6 +76,19 @@ def test_validation_rejects(change):
         lbm.validate(p)
     assert e.value.status == _lib.ERR_INVALID_ARG
     assert _lib.lib.lbm_last_error().decode()
+
+
+def test_mrt_defaults_are_the_papers_rates():
+    """Sec. 2.1: S = diag(1, 1.1, 1.1, 1, 1.1, 1, 1.1, 1/tau, 1/tau), the
+    shear entries stored as 0 (= 1/tau); BGK is the default operator."""
+    p = lbm.make_params(**WORKLOADS["cyl_d10"])
+    assert p.collision == _lib.COLLISION_BGK
+    assert list(p.s_rates) == [1, 1.1, 1.1, 1, 1.1, 1, 1.1, 0, 0]
+    p.collision = _lib.COLLISION_MRT
+    lbm.validate(p)
+    # conserved-moment rates are not checked: they multiply zero
+    p.s_rates[0] = p.s_rates[3] = p.s_rates[5] = -7.0
+    lbm.validate(p)
 
 
 def test_validation_rejects_wrong_struct_size():

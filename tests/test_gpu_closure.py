@@ -175,10 +175,18 @@ def _trunc(d=10):
     return dict(truncated_window(d, u=0.05), tau=0.62, outlet_mode=lbm.OUTLET_COPY_UNKNOWN)
 
 
-def test_zero_closure_reproduces_the_plain_run_bitwise():
+@pytest.mark.parametrize("two_step", [False, True])
+def test_zero_closure_reproduces_the_plain_run_bitwise(two_step):
+    """An untrained network (last layer zero) changes nothing; with the
+    closure on, steps run one per launch, and they still match a plain run on
+    the two-step kernel bit for bit."""
     kw = _trunc()
     a = lbm.Lattice(lbm.make_params(**kw))
     b = lbm.Lattice(lbm.make_params(**kw))
+    if two_step:
+        t2 = [v for v in range(1, lbm.num_variants() + 1) if lbm.variant_name(v) == "t2_h4"][0]
+        a.set_variant(t2)
+        b.set_variant(t2)
     net = lbm.Mlp(omlp.init(12))  # last layer zero
     norm = np.concatenate([np.zeros(36), np.ones(36), np.full(3, 0.01)])
     b.enable_closure(net, norm)

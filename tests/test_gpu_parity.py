@@ -6,65 +6,15 @@ Tolerance: |d rho|, |d u| and |d f*| <= 1e-5 after the stated number of steps
 Integer outputs (geometry, step counters, divergence step) must match exactly;
 repeated runs and kernel variants must match bit for bit.
 """
-import sys
-
 import numpy as np
 import pytest
 
 import oracle
 import paper_2605_02185_amd as lbm
 from lbm_inputs import WORKLOADS, channel, perturbed_populations
+from parity_util import ALL_WALLS, TOL, WT, _oracle_kwargs, compare_state, note, run_both
 
 pytestmark = pytest.mark.gpu
-
-# Table 1 weights, typed in from the paper (k = i - 1).
-WT = [4 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 36, 1 / 36, 1 / 36, 1 / 36]
-TOL = 1e-5
-ALL_WALLS = [lbm.WALL_FREE_SLIP, lbm.WALL_PERIODIC, lbm.WALL_NEBB, lbm.WALL_MOVING_BB]
-
-
-def note(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
-
-
-def _oracle_kwargs(kw):
-    return {k: v for k, v in kw.items() if k != "hist_capacity"}
-
-
-def run_both(kw, steps, seed=None, amp=0.05):
-    """Run the GPU and the oracle from the same state; returns both objects
-    after `steps` steps plus the two force histories."""
-    note(f"parity case {kw} steps={steps} seed={seed}")
-    lat = lbm.Lattice(lbm.make_params(**kw))
-    o = oracle.Oracle(oracle.OracleParams(**_oracle_kwargs(kw)))
-    if seed is not None:
-        f0 = perturbed_populations(seed, kw["ny"], kw["nx"], WT, amp, dtype=np.float32)
-        lat.set_populations(f0)
-        o.set_fstar(f0.astype(np.float64))
-    lat.step(steps)
-    g = lat.forces() if steps else (np.zeros(0),) * 4
-    ofx, ofy, bad = o.step(steps)
-    assert bad == 0
-    return lat, o, g, (ofx, ofy)
-
-
-def compare_state(lat, o, solid=None, tol=TOL):
-    rho, ux, uy = lat.fields()
-    orho, oux, ouy = o.fields()
-    f = lat.get_populations(np.float64)
-    of = o.get_fstar()
-    fluid = np.ones_like(orho, dtype=bool) if solid is None else solid == 0
-    errs = {
-        "rho": np.abs(rho - orho)[fluid].max(),
-        "ux": np.abs(ux - oux)[fluid].max(),
-        "uy": np.abs(uy - ouy)[fluid].max(),
-        "f": np.abs(f - of)[:, fluid].max(),
-    }
-    note(f"  max errors {errs}")
-    for k, v in errs.items():
-        assert v <= tol, (k, v)
-    return errs
 
 
 # ------------------------------------------------------------------ boxes
@@ -266,3 +216,57 @@ def test_graph_replay_matches_plain_launches():
     for x, y in zip(a.forces(), b.forces()):
         assert np.array_equal(x, y)
     assert a.t == b.t == 527
+
+
+# ------------------------------------------- two steps per launch
+TWO_STEP = [v for v in range(1, lbm.num_variants() + 1) if lbm.variant_name(v).startswith("t2_")]
+
+
+def _two_step_cases():
+    cases = []
+    for wall in ALL_WALLS:
+        for outlet in (lbm.OUTLET_COPY_ALL, lbm.OUTLET_COPY_UNKNOWN):
+            cases.append(dict(channel(6, u=0.06), tau=0.6, wall=wall, outlet_mode=outlet))
+    cases += [
+        dict(nx=3, ny=3, tau=0.62, u_in=0.0, x_periodic=True, wall=lbm.WALL_PERIODIC),
+        dict(nx=64, ny=5, tau=0.62, u_in=0.0, x_periodic=True, wall=lbm.WALL_PERIODIC),
+        dict(nx=125, ny=70, tau=0.7, u_in=0.04, x_periodic=True, wall=lbm.WALL_NEBB, u_wall_bottom=0.0),
+        dict(nx=300, ny=37, tau=0.7, u_in=0.04, x_periodic=True, wall=lbm.WALL_MOVING_BB, u_wall_bottom=0.0),
+        dict(nx=63, ny=9, tau=0.6, u_in=0.05, wall=lbm.WALL_FREE_SLIP),  # outlet at lane 62 of one strip
+        dict(nx=3, ny=3, tau=0.8, u_in=0.05, wall=lbm.WALL_NEBB),
+        dict(channel(6, u=0.06), tau=0.52, collision=lbm.COLLISION_MRT,
+             s_rates=(1, 1.1, 1.1, 1, 1.1, 1, 1.1, 0, 0)),
+    ]
+    return cases
+
+
+@pytest.mark.parametrize("case", range(len(_two_step_cases())))
+def test_two_step_variants_match_one_step_bitwise(case):
+    """The two-step kernels (f*(t+1) kept in registers) give the one-step
+    kernel's populations and force history bit for bit, for every wall and
+    outlet treatment, periodic boxes down to 3 x 3, odd step counts (the last
+    step then runs alone) and graph replay."""
+    kw = _two_step_cases()[case]
+    steps = 131  # two 64-step graphs, then a pair and a single step
+    seed = 500 + case
+    ref = _run_gpu(kw, steps, 0, seed)
+    for v in TWO_STEP:
+        note(f"  {kw} variant {lbm.variant_name(v)}")
+        f, forces = _run_gpu(kw, steps, v, seed)
+        assert np.array_equal(f, ref[0]), v
+        for a, b in zip(forces, ref[1]):
+            if a is not None:
+                assert np.array_equal(a, b), v
+
+
+def test_default_variant_follows_the_lattice_size():
+    """Two steps per launch from 2^20 nodes on, one below; variant 0 restores
+    the default."""
+    small = lbm.Lattice(lbm.make_params(**WORKLOADS["cyl_d10"]))
+    big = lbm.Lattice(lbm.make_params(**WORKLOADS["cyl_d40"]))
+    assert lbm.variant_name(small.variant) == "v1_ty1_nt"
+    assert lbm.variant_name(big.variant) == "t2_h4"
+    big.set_variant(1)
+    assert big.variant == 1
+    big.set_variant(0)
+    assert lbm.variant_name(big.variant) == "t2_h4"

@@ -9,59 +9,15 @@ about six periods) takes minutes of host time for the oracle; it runs when
 LBM_SLOW=1 is set.
 """
 import os
-import sys
 
-import numpy as np
 import pytest
 
 import oracle
 import paper_2605_02185_amd as lbm
 from lbm_inputs import WORKLOADS, channel
-from oracle import stats as ostats
+from parity_util import note, window_parity
 
 pytestmark = pytest.mark.gpu
-
-
-def note(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
-
-
-def established(cl, n=3, tol=0.02):
-    """The lift amplitude of each of the last n+1 periods, cut at successive
-    upward crossings of the mean, stays within tol of the last one."""
-    c = cl - cl.mean()
-    ups = [i for i in range(len(c) - 1) if c[i] < 0.0 <= c[i + 1]]
-    if len(ups) < n + 2:
-        return False, []
-    amps = [0.5 * np.ptp(cl[ups[-(i + 2)]:ups[-(i + 1)] + 1]) for i in range(n + 1)]
-    return max(abs(a / amps[0] - 1) for a in amps[1:]) < tol, amps
-
-
-def window_parity(kw, spin_up, window, periods, require_established=True):
-    note(f"shedding case {kw} spin-up {spin_up} window {window}")
-    d, u = kw["diameter"], kw["u_in"]
-    lat = lbm.Lattice(lbm.make_params(**kw))
-    lat.step(spin_up)
-    state = lat.get_populations(np.float64)
-    lat.step(window)
-    _, _, cd, cl = lat.forces(spin_up + 1, window)
-    gpu = lbm.shedding_stats(cd, cl, d, u, periods)
-    ok, amps = established(cl, n=min(3, periods - 1))
-    note(f"  GPU {gpu}, per-period amplitudes {np.round(amps, 5)}")
-
-    o = oracle.Oracle(oracle.OracleParams(**kw))
-    o.set_fstar(state)
-    fx, fy, bad = o.step(window)
-    assert bad == 0
-    ocd, ocl = ostats.coefficients(fx, fy, u, d)
-    ora = ostats.shedding(ocd, ocl, d, u, periods)
-    note(f"  oracle {ora}")
-    for k in ("mean_cd", "cl_amp", "st"):
-        assert gpu[k] == pytest.approx(ora[k], rel=0.01), k
-    if require_established:
-        assert ok, "shedding not established at the start of the window"
-    return gpu
 
 
 @pytest.mark.timeout(600)
