@@ -676,15 +676,18 @@ __device__ __forceinline__ void bulk_wave(const StepArgs& a, int strip, int seg)
   const int y0 = seg * H;
   const int x = xs - 1 + lane;
   const bool out_col = lane >= 1 && lane <= kStrip2;
-  float w[3][9], pre[3][9], out[H][9];
-  load_pull(a, x, y0 - 1, pre[0]);
-  load_pull(a, x, y0, pre[1]);
+  // short segments issue every load of the wave first; longer ones keep
+  // two rows in flight
+  constexpr int AHEAD = H <= 6 ? H + 2 : 2, R = AHEAD + 1;
+  float w[3][9], pre[R][9], out[H][9];
+#pragma unroll
+  for (int i = 0; i < AHEAD; ++i) load_pull(a, x, y0 - 1 + i, pre[i]);
   bool bad1 = false, bad2 = false;
 #pragma unroll
   for (int i = 0; i < H + 2; ++i) {  // f*(t+1) of row y0-1+i
-    if (i + 2 < H + 2) load_pull(a, x, y0 + 1 + i, pre[(i + 2) % 3]);
+    if (i + AHEAD < H + 2) load_pull(a, x, y0 - 1 + i + AHEAD, pre[(i + AHEAD) % R]);
     bool b1 = false;
-    collide(pre[i % 3], a.p, w[i % 3], b1);
+    collide(pre[i % R], a.p, w[i % 3], b1);
     if (i >= 1 && i <= H) bad1 |= b1;
     if (i >= 2) {  // f*(t+2) of row y0+i-2
       const float(&wa)[9] = w[(i + 1) % 3];
@@ -966,6 +969,7 @@ constexpr Variant kVariants[] = {
     {"v1_ty1_xrow_nt", 256, 1, 1, 2, 1, 1},
     {"v2_ty1_xrow_nt", 512, 1, 2, 2, 1, 1},
     {"t2_h4", kStrip2, 4, 1, 0, 0, 2},
+    {"t2_h6", kStrip2, 6, 1, 0, 0, 2},
     {"t2_h8", kStrip2, 8, 1, 0, 0, 2},
     {"t2_h8_nt", kStrip2, 8, 1, 0, 1, 2},
     {"t2_h16", kStrip2, 16, 1, 0, 0, 2},
@@ -1024,6 +1028,7 @@ hipError_t launch_step(const StepArgs& a, int v, hipStream_t s) {
     return hipGetLastError();                                              \
   }
     LBM_T2(false, 4)
+    LBM_T2(false, 6)
     LBM_T2(false, 8)
     LBM_T2(true, 8)
     LBM_T2(false, 16)
