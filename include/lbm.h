@@ -317,8 +317,9 @@ lbm_status lbm_column_moments(const float* x, int64_t M, int32_t ncols, double* 
 lbm_status lbm_sample_boundary(lbm_ctx* full, int32_t ox, int32_t oy, int32_t wnx, int32_t wny,
                                const int32_t* nodes, int64_t n, float* feat, float* target);
 
-/* Switch the context to the learned closure: every step first evaluates the
- * network on all boundary nodes from the current state, then adds
+/* Switch the context to the learned closure: every step (or every interval
+ * steps, lbm_closure_set_interval) first evaluates the network on all
+ * boundary nodes from the current state, then adds
  * out_scale * output to the plain values of the missing populations on the
  * boundaries selected by the bit mask `boundaries` (1 top, 2 bottom, 4
  * outlet; the others keep their plain treatment).
@@ -334,6 +335,15 @@ lbm_status lbm_closure_disable(lbm_ctx* ctx);
  * default) applies each prediction as is.  Row nodes within `taper` nodes of
  * the inlet or the outlet column keep the plain treatment (default 0). */
 lbm_status lbm_closure_set_filter(lbm_ctx* ctx, float beta, int32_t taper);
+
+/* Evaluate the network only every `interval` steps (1, 2, 4, 8, 16, 32 or
+ * 64; default 1) and apply the held residual in between, at the steps whose
+ * index since lbm_create is a multiple of `interval`.  With an even interval
+ * the context keeps its two-step launches (pairs that start on an evaluation
+ * step), the held residual entering both steps of a pair; the results are
+ * the same bit for bit as with one step per launch.  beta applies per
+ * evaluation. */
+lbm_status lbm_closure_set_interval(lbm_ctx* ctx, int32_t interval);
 
 /* Residuals the closure computes from the current state, host [nb][3]. */
 lbm_status lbm_closure_residuals(lbm_ctx* ctx, float* out);

@@ -160,6 +160,10 @@ class Lattice:
     def set_closure_filter(self, beta: float = 1.0, taper: int = 0):
         check(_lib.lib.lbm_closure_set_filter(self._h, beta, taper))
 
+    def set_closure_interval(self, interval: int = 1):
+        """Evaluate the network every `interval` steps (a divisor of 64)."""
+        check(_lib.lib.lbm_closure_set_interval(self._h, interval))
+
     def disable_closure(self):
         check(_lib.lib.lbm_closure_disable(self._h))
         self._mlp_ref = None

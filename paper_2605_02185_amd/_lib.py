@@ -121,6 +121,7 @@ def _load():
         "lbm_column_moments": (i32, [vp, i64, i32, vp, vp, vp]),
         "lbm_sample_boundary": (i32, [vp, i32, i32, i32, i32, vp, i64, vp, vp]),
         "lbm_closure_enable": (i32, [vp, vp, vp, i32]),
+        "lbm_closure_set_interval": (i32, [vp, i32]),
         "lbm_closure_disable": (i32, [vp]),
         "lbm_closure_set_filter": (i32, [vp, ctypes.c_float, i32]),
         "lbm_closure_residuals": (i32, [vp, vp]),

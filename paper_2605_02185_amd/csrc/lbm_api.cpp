@@ -168,6 +168,7 @@ struct lbm_ctx {
   int closure_mask = 7;
   float closure_beta = 1.0f;
   int closure_taper = 0;
+  int closure_interval = 1;
   float* d_norm = nullptr;
   float* d_resid = nullptr;
 };
@@ -446,10 +447,15 @@ lbm_status lbm_set_variant(lbm_ctx* c, int32_t v) {
 
 namespace {
 
-// Two steps fit in one launch when the variant takes two, the learned closure
-// (which needs the state before every step) is off and the ring has room.
+// The learned closure is evaluated before the steps whose index is a multiple
+// of its interval.
+bool closure_due(const lbm_ctx* c) { return c->mlp && c->step % c->closure_interval == 0; }
+
+// Two steps fit in one launch when the variant takes two, the ring has room
+// and no closure evaluation falls between them.
 bool pairable(const lbm_ctx* c) {
-  return lbm::variant(c->variant).steps == 2 && !c->mlp && c->pending + 2 <= lbm::kRing;
+  if (lbm::variant(c->variant).steps != 2 || c->pending + 2 > lbm::kRing) return false;
+  return !c->mlp || (c->closure_interval % 2 == 0 && (c->step + 1) % c->closure_interval != 0);
 }
 
 // Enqueues k = 1 or 2 steps (k = 2 only when pairable) on stream s, buffers by
@@ -476,9 +482,11 @@ lbm_status enqueue_step(lbm_ctx* c, hipStream_t s, int k = 1) {
     lbm::tiling_for_variant(c->geo, v, &a.t);
   }
   if (c->mlp) {
-    const lbm::MlpDevice md = lbm::mlp_device(c->mlp);
-    HIP_TRY(lbm::launch_closure(a.A, c->geo, md.Wb, md.master, c->d_norm, c->closure_mask, c->closure_beta,
-                                c->closure_taper, c->d_resid, s));
+    if (closure_due(c)) {
+      const lbm::MlpDevice md = lbm::mlp_device(c->mlp);
+      HIP_TRY(lbm::launch_closure(a.A, c->geo, md.Wb, md.master, c->d_norm, c->closure_mask, c->closure_beta,
+                                  c->closure_taper, c->d_resid, s));
+    }
     a.closure = c->d_resid;
   }
   HIP_TRY(lbm::launch_step(a, v, s));
@@ -614,6 +622,17 @@ lbm_status lbm_closure_set_filter(lbm_ctx* c, float beta, int32_t taper) {
   return LBM_OK;
 }
 
+lbm_status lbm_closure_set_interval(lbm_ctx* c, int32_t interval) {
+  if (check_ctx(c)) return LBM_ERR_INVALID_ARG;
+  if (interval < 1 || interval > lbm::kRing || lbm::kRing % interval != 0)
+    return fail(LBM_ERR_INVALID_ARG, "interval %d must divide %d", interval, lbm::kRing);
+  lbm_status st = flush(c);
+  if (st != LBM_OK) return st;
+  drop_graphs(c);
+  c->closure_interval = interval;
+  return LBM_OK;
+}
+
 lbm_status lbm_closure_disable(lbm_ctx* c) {
   if (check_ctx(c)) return LBM_ERR_INVALID_ARG;
   lbm_status st = flush(c);
@@ -662,8 +681,10 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   if (check_ctx(c)) return LBM_ERR_INVALID_ARG;
   if (n < 0) return fail(LBM_ERR_INVALID_ARG, "n must be >= 0");
   int64_t i = 0;
-  // plain launches until the ring is empty, then whole graphs
-  while (i < n && c->pending != 0) {
+  // plain launches until the ring is empty (and, with a learned closure, the
+  // step index is a multiple of its interval, so that every graph replays
+  // the evaluations at the same places), then whole graphs
+  while (i < n && (c->pending != 0 || (c->mlp && c->step % c->closure_interval != 0))) {
     const int k = n - i >= 2 && pairable(c) ? 2 : 1;
     lbm_status st = enqueue_step(c, c->stream, k);
     if (st != LBM_OK) return st;

@@ -267,6 +267,33 @@ __device__ __forceinline__ void link_force(const Geometry& geo, double2* __restr
   partial[idx] = make_double2(Fx, Fy);
 }
 
+// Learned-closure residuals (when enabled) on the three missing populations
+// of a wall-row node (top row nodes 0 .. nx-3, bottom row nodes nx-2 ..
+// 2nx-5 of the closure's boundary numbering) and of an outlet node (nodes
+// 2(nx-2) ..).
+__device__ __forceinline__ void closure_row(const StepArgs& a, int x, int y, float (&g)[9]) {
+  if (!a.closure) return;
+  if (y == a.g.ny - 1) {
+    const float* r = a.closure + 3 * (x - 1);
+    g[4] += r[0];
+    g[7] += r[1];
+    g[8] += r[2];
+  } else {
+    const float* r = a.closure + 3 * ((a.g.nx - 2) + (x - 1));
+    g[2] += r[0];
+    g[6] += r[1];
+    g[5] += r[2];
+  }
+}
+
+__device__ __forceinline__ void closure_outlet(const StepArgs& a, int y, float (&g)[9]) {
+  if (!a.closure) return;
+  const float* r = a.closure + 3 * (2 * (a.g.nx - 2) + (y - 1));
+  g[3] += r[0];
+  g[6] += r[1];
+  g[7] += r[2];
+}
+
 // Streamed and row-corrected populations of node (x, y).  With a learned
 // closure the network's residuals are added to the wall treatment's values
 // of the three missing populations (top row nodes 0 .. nx-3, bottom row
@@ -282,19 +309,7 @@ __device__ __forceinline__ void gather(const StepArgs& a, int x, int y, uint16_t
       for (int k = 0; k < 9; ++k) fs[k] = load(a.A, a.g, k, x, y);
     }
     wall_bc(a.p, y == a.g.ny - 1, fs, g);
-    if (a.closure) {
-      if (y == a.g.ny - 1) {
-        const float* r = a.closure + 3 * (x - 1);
-        g[4] += r[0];
-        g[7] += r[1];
-        g[8] += r[2];
-      } else {
-        const float* r = a.closure + 3 * ((a.g.nx - 2) + (x - 1));
-        g[2] += r[0];
-        g[6] += r[1];
-        g[5] += r[2];
-      }
-    }
+    closure_row(a, x, y, g);
   }
 }
 
@@ -326,12 +341,7 @@ __device__ __forceinline__ void general_update(const StepArgs& a, int x, int y, 
       g[4] = own[4];
       g[5] = own[5];
       g[8] = own[8];
-      if (a.closure) {  // outlet nodes 2(nx-2) .. of the closure numbering
-        const float* r = a.closure + 3 * (2 * (nx - 2) + (y - 1));
-        g[3] += r[0];
-        g[6] += r[1];
-        g[7] += r[2];
-      }
+      closure_outlet(a, y, g);
     }
   } else {
     gather(a, x, y, fl, g);
@@ -618,7 +628,10 @@ __device__ __forceinline__ void second_update(const StepArgs& a, int x, int y, b
   }
   const bool wall_row = a.p.wall != kWallPeriodic && (y == 0 || y == ny - 1);
   const bool wall_x = a.p.x_periodic || (x >= 1 && x <= nx - 2);
-  if (active && wall_row && wall_x) wall_bc(a.p, y == ny - 1, w1, g);
+  if (active && wall_row && wall_x) {
+    wall_bc(a.p, y == ny - 1, w1, g);
+    closure_row(a, x, y, g);
+  }
   // Eq. 13: the corrected populations of x = nx-2 are the left lane's g
   if (__any(outlet)) {
     float G[9];
@@ -629,6 +642,7 @@ __device__ __forceinline__ void second_update(const StepArgs& a, int x, int y, b
         g[3] = G[3];
         g[6] = G[6];
         g[7] = G[7];
+        closure_outlet(a, y, g);
       } else {
 #pragma unroll
         for (int k = 0; k < 9; ++k) g[k] = G[k];
