@@ -752,7 +752,13 @@ __device__ __forceinline__ void general_wave(const StepArgs& a, int segment, int
   prefetch_bulk(a, x, row_of(y0 - 1), pre);
   prefetch_bulk(a, x, row_of(y0), pre1);
   bool bad1 = false, bad2 = false;
-  for (int r = y0 - 1; r <= y1; ++r) {
+  // unrolled, with the output rows held until the last load has been issued
+  // (a wait for a load also waits for every older store)
+  float outb[kSub2][9];
+#pragma unroll
+  for (int i = 0; i < kSub2 + 2; ++i) {
+    const int r = y0 - 1 + i;
+    if (r > y1) break;  // short sub-segment at the lattice's last rows
     float nxt[9];
     prefetch_bulk(a, x, row_of(r + 2), nxt);
 #pragma unroll
@@ -768,13 +774,12 @@ __device__ __forceinline__ void general_wave(const StepArgs& a, int segment, int
       pre[k] = pre1[k];
       pre1[k] = nxt[k];
     }
-    if (r > y0) {
-      const int y2 = r - 1;
-      float out[9];
-      second_update(a, x, y2, col_ok, out_col, w0, w1, w2, out, bad2);
-      if (out_col) store9<NT>(a.B, P, (uint32_t)y2 * Wp + (uint32_t)x, out);
-    }
+    if (i >= 2) second_update(a, x, r - 1, col_ok, out_col, w0, w1, w2, outb[i - 2], bad2);
   }
+  if (out_col)
+#pragma unroll
+    for (int j = 0; j < kSub2; ++j)
+      if (y0 + j < y1) store9<NT>(a.B, P, (uint32_t)(y0 + j) * Wp + (uint32_t)x, outb[j]);
   if (bad1) atomicMin(a.bad, a.slot);
   if (bad2) atomicMin(a.bad, a.slot + 1);
 }
@@ -982,6 +987,7 @@ constexpr Variant kVariants[] = {
     {"v4_ty1_xcd_nt", 1024, 1, 4, 1, 1, 1},
     {"v1_ty1_xrow_nt", 256, 1, 1, 2, 1, 1},
     {"v2_ty1_xrow_nt", 512, 1, 2, 2, 1, 1},
+    {"v1_ty1_xcd", 256, 1, 1, 1, 0, 1},
     {"t2_h4", kStrip2, 4, 1, 0, 0, 2},
     {"t2_h6", kStrip2, 6, 1, 0, 0, 2},
     {"t2_h8", kStrip2, 8, 1, 0, 0, 2},
@@ -994,12 +1000,15 @@ constexpr Variant kVariants[] = {
 int num_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 const Variant& variant(int v) { return kVariants[v - 1]; }
 
-// The two-step kernel pays once the interior segments fill the chip (measured
-// faster from 1.4 M nodes on, slower at 86 k); the one-step kernel below.
+// The two-step kernel pays once its interior segments fill the chip (1.3x at
+// 5.5 M nodes, even at 1.4 M, slower below).  Smaller lattices live in the
+// caches: there the one-step kernel with cached stores and each XCD on its
+// own band of rows is fastest (10-25 % over the plain order at 86 k-800 k
+// nodes; the plain order wins once the lattice streams from HBM).
 int default_variant(int64_t nodes) {
-  if (nodes >= ((int64_t)1 << 20))
-    for (int v = 1; v <= num_variants(); ++v)
-      if (std::strcmp(kVariants[v - 1].name, "t2_h4") == 0) return v;
+  const char* want = nodes >= ((int64_t)1 << 20) ? "t2_h4" : "v1_ty1_xcd";
+  for (int v = 1; v <= num_variants(); ++v)
+    if (std::strcmp(kVariants[v - 1].name, want) == 0) return v;
   return 1;
 }
 

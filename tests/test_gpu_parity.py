@@ -260,11 +260,11 @@ def test_two_step_variants_match_one_step_bitwise(case):
 
 
 def test_default_variant_follows_the_lattice_size():
-    """Two steps per launch from 2^20 nodes on, one below; variant 0 restores
-    the default."""
+    """Two steps per launch from 2^20 nodes on, one below (cached stores, XCD
+    bands); variant 0 restores the default."""
     small = lbm.Lattice(lbm.make_params(**WORKLOADS["cyl_d10"]))
     big = lbm.Lattice(lbm.make_params(**WORKLOADS["cyl_d40"]))
-    assert lbm.variant_name(small.variant) == "v1_ty1_nt"
+    assert lbm.variant_name(small.variant) == "v1_ty1_xcd"
     assert lbm.variant_name(big.variant) == "t2_h4"
     big.set_variant(1)
     assert big.variant == 1
