@@ -23,6 +23,7 @@ _LIB_PATH = os.path.join(_HERE, "liblbm_oracle.so")
 
 WALL_FREE_SLIP, WALL_PERIODIC, WALL_NEBB, WALL_MOVING_BB = 0, 1, 2, 3
 BGK, MRT = 0, 1
+BB_HALFWAY, BB_INTERP = 0, 1
 # Relaxation rates of the paper's MRT (Sec. 2.1); the last two (shear) are 1/tau.
 PAPER_S = (1.0, 1.1, 1.1, 1.0, 1.1, 1.0, 1.1, 0.0, 0.0)
 OUTLET_COPY_ALL, OUTLET_COPY_UNKNOWN = 0, 1
@@ -59,6 +60,8 @@ class _Params(ctypes.Structure):
         ("gy", ctypes.c_double),
         ("collision", ctypes.c_int),
         ("s_rates", ctypes.c_double * 9),
+        ("bounce", ctypes.c_int),
+        ("q_fixed", ctypes.c_double),
     ]
 
 
@@ -91,6 +94,8 @@ def _load():
     lib.oracle_tau.restype = ctypes.c_double
     lib.oracle_threads.restype = ctypes.c_int
     lib.oracle_mrt_matrix.argtypes = [dp]
+    lib.oracle_links.restype = ctypes.c_long
+    lib.oracle_links.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.oracle_mrt_meq.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
     _lib = lib
     return lib
@@ -118,6 +123,8 @@ class OracleParams:
     gy: float = 0.0
     collision: int = BGK
     s_rates: tuple = PAPER_S
+    bounce: int = BB_HALFWAY
+    q_fixed: float = 0.0
 
     def _c(self) -> _Params:
         d = self.diameter
@@ -128,7 +135,7 @@ class OracleParams:
             self.u_in, self.re, self.tau, self.wall,
             self.u_wall_top, self.u_wall_bottom, self.outlet_mode,
             1 if self.x_periodic else 0, self.perturb_amp, self.gx, self.gy,
-            self.collision, (ctypes.c_double * 9)(*self.s_rates),
+            self.collision, (ctypes.c_double * 9)(*self.s_rates), self.bounce, self.q_fixed,
         )
 
 
@@ -184,6 +191,16 @@ class Oracle:
         if not self._h:
             raise ValueError("oracle_create rejected the parameters")
         self.tau = tau_of(p)
+
+    def links(self):
+        """(node index y*nx + x, direction k, wall fraction q) of every
+        fluid-to-solid link, in the oracle's order."""
+        n = self._lib.oracle_links(self._h, None, None, None)
+        node = np.empty(n, np.int64)
+        k = np.empty(n, np.int32)
+        q = np.empty(n, np.float64)
+        self._lib.oracle_links(self._h, node.ctypes.data, k.ctypes.data, q.ctypes.data)
+        return node, k, q
 
     def close(self):
         if self._h:

@@ -111,6 +111,9 @@ struct oracle {
   long n_links;
   size_t* link_node;
   int* link_dir;
+  double* link_q;       /* wall fraction of each link (interpolated bounce-back) */
+  double* node_q;       /* [ny][nx][9]: q of the link (node, k), NaN elsewhere */
+  int own_mask;         /* the caller supplied the solid mask */
 };
 
 static size_t node(const oracle* o, int x, int y) { return (size_t)y * o->nx + x; }
@@ -184,6 +187,7 @@ oracle* oracle_create(const oracle_params* p, const unsigned char* solid) {
   else
     oracle_digitise(p, o->solid);
   init_equilibrium(o);
+  o->own_mask = solid != NULL;
   if (build_links(o) != 0) {
     oracle_destroy(o);
     return NULL;
@@ -200,6 +204,8 @@ void oracle_destroy(oracle* o) {
   free(o->rho_t);
   free(o->link_node);
   free(o->link_dir);
+  free(o->link_q);
+  free(o->node_q);
   free(o);
 }
 
@@ -289,6 +295,27 @@ static int neighbour(const oracle* o, int x, int y, int k, int* xo, int* yo) {
   return 1;
 }
 
+/* Sec. 2.4 (link-wise approach, Bouzidi, Firdaouss & Lallemand 2001): the
+ * wall cuts the link from the fluid node x along c_k at x + q c_k.  For the
+ * cylinder, the circle |p - c| = D/2 with c = (cx2, cy2)/2; in doubled
+ * coordinates X = 2x - cx2, Y = 2y - cy2 the cut solves
+ * (X + 2 q cx)^2 + (Y + 2 q cy)^2 = D^2, whose smaller root lies in (0, 1]
+ * because x is outside the digitised disk and x + c_k inside or on it. */
+static double link_fraction(const oracle* o, int x, int y, int k) {
+  if (o->p.q_fixed > 0.0) return o->p.q_fixed;
+  if (o->own_mask || o->p.diameter <= 0) return 0.5;
+  double X = 2.0 * x - o->p.cx2, Y = 2.0 * y - o->p.cy2, D = o->p.diameter;
+  double a = 4.0 * (CX[k] * CX[k] + CY[k] * CY[k]);
+  double b = 4.0 * (X * CX[k] + Y * CY[k]);
+  double c = X * X + Y * Y - D * D;
+  double disc = b * b - 4.0 * a * c;
+  if (disc < 0.0) disc = 0.0;
+  double q = (-b - sqrt(disc)) / (2.0 * a);
+  if (q <= 0.0) q = 1e-12;
+  if (q > 1.0) q = 1.0;
+  return q;
+}
+
 /* Every link from a fluid node into a solid node, all eight directions, in
  * row-major node order. */
 static int build_links(oracle* o) {
@@ -305,6 +332,8 @@ static int build_links(oracle* o) {
           if (pass == 1) {
             o->link_node[n] = m;
             o->link_dir[n] = k;
+            o->link_q[n] = link_fraction(o, x, y, k);
+            if (o->node_q) o->node_q[m * 9 + k] = o->link_q[n];
           }
           ++n;
         }
@@ -313,21 +342,65 @@ static int build_links(oracle* o) {
       cap = n > 0 ? n : 1;
       o->link_node = (size_t*)malloc(cap * sizeof(size_t));
       o->link_dir = (int*)malloc(cap * sizeof(int));
-      if (!o->link_node || !o->link_dir) return -1;
+      o->link_q = (double*)malloc(cap * sizeof(double));
+      if (!o->link_node || !o->link_dir || !o->link_q) return -1;
+      if (o->p.bounce == ORACLE_BB_INTERP) {
+        size_t nn9 = (size_t)o->nx * o->ny * 9;
+        o->node_q = (double*)malloc(nn9 * sizeof(double));
+        if (!o->node_q) return -1;
+        for (size_t i = 0; i < nn9; ++i) o->node_q[i] = NAN;
+      }
     }
   }
   o->n_links = n;
   return 0;
 }
 
-/* O2: Eq. 14 summed over the links.  The population leaving along c_k is
- * f*_k, the one coming back along -c_k has the same value (stationary wall,
- * same step), so the momentum given to the body per link is 2 c_k f*_k. */
+long oracle_links(const oracle* o, long* out_node, int* out_dir, double* out_q) {
+  for (long i = 0; i < o->n_links; ++i) {
+    if (out_node) out_node[i] = (long)o->link_node[i];
+    if (out_dir) out_dir[i] = o->link_dir[i];
+    if (out_q) out_q[i] = o->link_q[i];
+  }
+  return o->n_links;
+}
+
+/* The population that comes back to fluid node n along -c_k after its
+ * post-collision f*_k(n) has met the wall of link (n, k) with fraction q.
+ * Half-way bounce-back: f*_k(n).  Interpolated (the linear scheme of Bouzidi
+ * et al.): for q < 1/2 the value is interpolated between n and the fluid node
+ * n - c_k behind it, 2 q f*_k(n) + (1 - 2q) f*_k(n - c_k); for q >= 1/2
+ * between the reflected value and the node's own opposite population,
+ * f*_k(n)/(2q) + (2q - 1)/(2q) f*_opp(k)(n).  Both give f*_k(n) at q = 1/2.
+ * Where n - c_k is not a fluid node of the lattice, half-way bounce-back. */
+static double bounced(const oracle* o, int x, int y, int k, double q) {
+  size_t n = node(o, x, y);
+  double fk = o->fs[n * 9 + k];
+  if (o->p.bounce != ORACLE_BB_INTERP) return fk;
+  if (q < 0.5) {
+    int xb, yb;
+    if (!neighbour(o, x, y, OPP[k], &xb, &yb) || o->solid[node(o, xb, yb)]) return fk;
+    return 2.0 * q * fk + (1.0 - 2.0 * q) * o->fs[node(o, xb, yb) * 9 + k];
+  }
+  return fk / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * o->fs[n * 9 + OPP[k]];
+}
+
+/* O2: Eq. 14 summed over the links: the population leaving along c_k is
+ * f*_k (in), the one coming back along -c_k is the bounced value (out), and
+ * the body receives (f_in + f_out) c_k.  With half-way bounce-back both are
+ * f*_k (stationary wall, same step): 2 c_k f*_k. */
 static void force(const oracle* o, double* fx, double* fy) {
   double sx = 0.0, sy = 0.0;
   for (long i = 0; i < o->n_links; ++i) {
     int k = o->link_dir[i];
     double f = o->fs[o->link_node[i] * 9 + k];
+    if (o->p.bounce == ORACLE_BB_INTERP) {
+      int x = (int)(o->link_node[i] % o->nx), y = (int)(o->link_node[i] / o->nx);
+      double b = bounced(o, x, y, k, o->link_q[i]);
+      sx += CX[k] * (f + b);
+      sy += CY[k] * (f + b);
+      continue;
+    }
     sx += 2.0 * CX[k] * f;
     sy += 2.0 * CY[k] * f;
   }
@@ -335,7 +408,8 @@ static void force(const oracle* o, double* fx, double* fy) {
   *fy = sy;
 }
 
-/* O3: push streaming with half-way bounce-back at solid nodes. */
+/* O3: push streaming with bounce-back (half-way or interpolated) at solid
+ * nodes. */
 static void stream(oracle* o) {
   long total = (long)o->nx * o->ny * 9;
 #pragma omp parallel for schedule(static)
@@ -350,7 +424,7 @@ static void stream(oracle* o) {
         if (!neighbour(o, x, y, k, &xn, &yn)) continue; /* leaves the lattice */
         size_t m = node(o, xn, yn);
         if (o->solid[m])
-          o->g[n * 9 + OPP[k]] = o->fs[n * 9 + k];
+          o->g[n * 9 + OPP[k]] = o->node_q ? bounced(o, x, y, k, o->node_q[n * 9 + k]) : o->fs[n * 9 + k];
         else
           o->g[m * 9 + k] = o->fs[n * 9 + k];
       }

@@ -37,6 +37,8 @@ enum { ORACLE_OUTLET_COPY_ALL = 0, ORACLE_OUTLET_COPY_UNKNOWN = 1 };
 
 enum { ORACLE_BGK = 0, ORACLE_MRT = 1 };
 
+enum { ORACLE_BB_HALFWAY = 0, ORACLE_BB_INTERP = 1 };
+
 typedef struct {
   int nx, ny;             /* lattice nodes x in [0,nx), y in [0,ny) */
   int diameter;           /* cylinder diameter in lattice units; 0 = no cylinder */
@@ -53,6 +55,10 @@ typedef struct {
   double gx, gy;          /* body-force acceleration (Guo forcing), test boxes only */
   int collision;          /* ORACLE_BGK (Eq. 2) or ORACLE_MRT (Eq. 6) */
   double s_rates[9];      /* MRT relaxation rates diag(S); entries 7 and 8 <= 0 mean 1/tau */
+  int bounce;             /* cylinder links: ORACLE_BB_HALFWAY or ORACLE_BB_INTERP (Sec. 2.4) */
+  double q_fixed;         /* interpolated links: > 0 gives every link this wall fraction
+                           * (test geometries); else q from the circle of the disk, or 1/2
+                           * when the caller supplies the solid mask */
 } oracle_params;
 
 typedef struct oracle oracle;
@@ -95,6 +101,12 @@ void oracle_set_fstar(oracle* o, const double* in);
  * moment-space equilibrium m_eq(rho, u, v) the oracle uses, for tests. */
 void oracle_mrt_matrix(double* M);
 void oracle_mrt_meq(double rho, double ux, double uy, double* meq);
+
+/* Wall fractions q of the links, in the order of the oracle's link list
+ * (row-major fluid nodes, directions 1..8): out_node[i] = y*nx + x,
+ * out_dir[i] = k (the link from that node along c_k ends in a solid node),
+ * out_q[i] = q.  Returns the number of links; arrays may be NULL to count. */
+long oracle_links(const oracle* o, long* out_node, int* out_dir, double* out_q);
 
 /* OpenMP threads the oracle's parallel loops use. */
 int oracle_threads(void);
