@@ -455,6 +455,13 @@ __device__ __forceinline__ void bulk_vec(const StepArgs& a, int x0, int y, bool&
   }
 }
 
+// Records a failed density check of step `slot` once per wave (one atomic
+// per wave rather than per node keeps a diverged lattice, where every node
+// fails, from serialising on the flag).  Every lane of the wave must call it.
+__device__ __forceinline__ void report_bad(int* flag, bool bad, int slot) {
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicMin(flag, slot);
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs (block id mod 8), and
 // each XCD has its own L2.  Two block-to-tile maps keep neighbouring tiles of
 // a row, which share the halo cache lines of the x-shifted planes, on one XCD:
@@ -502,7 +509,7 @@ __device__ __forceinline__ void process_tile(const StepArgs& a, int bx, int by) 
         bulk_vec<VX, NT>(a, x0, y, bad);
     }
   }
-  if (bad) atomicMin(a.bad, a.slot);
+  report_bad(a.bad, bad, a.slot);
 }
 
 template <int TY, int VX, bool NT>
@@ -720,12 +727,12 @@ __device__ __forceinline__ void bulk_wave(const StepArgs& a, int strip, int seg)
       collide(c, a.p, out[i - 2], bad2);
     }
   }
+  report_bad(a.bad, bad1 && out_col, a.slot);
+  report_bad(a.bad, bad2 && out_col, a.slot + 1);
   if (!out_col) return;
   const uint32_t P = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
 #pragma unroll
   for (int j = 0; j < H; ++j) store9<NT>(a.B, P, (uint32_t)(y0 + j) * Wp + (uint32_t)x, out[j]);
-  if (bad1) atomicMin(a.bad, a.slot);
-  if (bad2) atomicMin(a.bad, a.slot + 1);
 }
 
 // kSub2 rows of a segment that is not interior, with the boundary code.
@@ -780,8 +787,8 @@ __device__ __forceinline__ void general_wave(const StepArgs& a, int segment, int
 #pragma unroll
     for (int j = 0; j < kSub2; ++j)
       if (y0 + j < y1) store9<NT>(a.B, P, (uint32_t)(y0 + j) * Wp + (uint32_t)x, outb[j]);
-  if (bad1) atomicMin(a.bad, a.slot);
-  if (bad2) atomicMin(a.bad, a.slot + 1);
+  report_bad(a.bad, bad1, a.slot);
+  report_bad(a.bad, bad2, a.slot + 1);
 }
 
 // One launch, two steps.  The first blocks take the boundary sub-segments
