@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-ceiling reference")
     ap.add_argument("--no-graphs", action="store_true", help="plain launches instead of graph replay")
+    ap.add_argument("--ensemble", action="store_true",
+                    help="also time the 64-case ensemble (MRT, tau from Re) against 64 separate lattices")
     ap.add_argument("--closure", action="store_true",
                     help="also train and evaluate the learned boundary closure (about a minute)")
     args = ap.parse_args()
@@ -205,9 +207,46 @@ def main():
     lat.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    if args.ensemble:
+        out["ensemble"] = ensemble_result(torch, lbm)
     if args.closure:
         out["closure"] = closure_result()
     print(json.dumps(out), flush=True)
+
+
+def ensemble_result(torch, lbm, steps: int = 1280) -> dict:
+    """The 64 cylinder channels (D 8..32, Re 60..200, U = 0.05, tau from Re,
+    MRT with the rates of Sec. 2.1): one Ensemble against the same cases as
+    64 separate lattices stepped one after the other, both after 128 warm-up
+    steps; MLUPS over all nodes of all cases."""
+    from lbm_inputs import ensemble
+
+    cases = ensemble(mrt=True)
+    nodes = sum(c["nx"] * c["ny"] for c in cases)
+    ens = lbm.Ensemble([lbm.make_params(**c) for c in cases])
+    ens.step(128)
+    ens.sync()
+    t0 = time.perf_counter()
+    ens.step(steps)
+    ens.sync()
+    t_ens = time.perf_counter() - t0
+    ens.close()
+    lats = [lbm.Lattice(lbm.make_params(**c)) for c in cases]
+    for lat in lats:
+        lat.step(128)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for lat in lats:
+        lat.step(steps)
+    for lat in lats:
+        lat.sync()
+    t_sep = time.perf_counter() - t0
+    for lat in lats:
+        lat.close()
+    return {"cases": len(cases), "nodes": nodes, "steps": steps,
+            "mlups": round(nodes * steps / t_ens / 1e6, 1),
+            "separate_mlups": round(nodes * steps / t_sep / 1e6, 1),
+            "speedup": round(t_sep / t_ens, 3)}
 
 
 def closure_result() -> dict:

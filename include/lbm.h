@@ -57,6 +57,13 @@ typedef enum {
   LBM_OUTLET_COPY_UNKNOWN = 1 /* only W, NW, SW; all nine at the two outlet corners */
 } lbm_outlet;
 
+/* Cylinder wall treatment (Sec. 2.4). */
+typedef enum {
+  LBM_BOUNCE_HALFWAY = 0, /* half-way bounce-back on the staircase disk (the paper's choice) */
+  LBM_BOUNCE_INTERP = 1   /* link-wise interpolated bounce-back (Bouzidi, Firdaouss & Lallemand)
+                           * with the wall fraction q of each link from the circle */
+} lbm_bounce;
+
 /* Collision operator. */
 typedef enum {
   LBM_COLLISION_BGK = 0, /* single relaxation time 1/tau (Eq. 2) */
@@ -84,6 +91,8 @@ typedef struct {
    * and have no effect; entries 7 and 8 (the shear rates) <= 0 mean 1/tau,
    * so that tau sets the viscosity through Eq. 5 as for BGK. */
   double s_rates[9];
+  int32_t bounce;        /* lbm_bounce */
+  int32_t reserved1;
 } lbm_params;
 
 /* Defaults: D = 0, centre 21*D doubled (10.5 D), U = 0.1, Re = 100, tau
@@ -94,7 +103,8 @@ void lbm_params_init(lbm_params* p);
 
 /* Host-only check of a parameter set (no GPU needed).  Rejects nx or ny < 3,
  * tau <= 1/2, U outside [0, 1/sqrt(3)), an unknown wall, outlet or collision
- * mode, an MRT rate of a non-conserved moment outside (0, 2), a
+ * mode, an MRT rate of a non-conserved moment outside (0, 2), an unknown
+ * bounce-back mode, a
  * cylinder with a solid node outside [3, nx-4] x [3, ny-4] (so that two fluid
  * nodes separate it from every edge row and column), and hist_capacity < 1. */
 lbm_status lbm_validate_params(const lbm_params* p);
@@ -121,7 +131,8 @@ void lbm_destroy(lbm_ctx* ctx);
 
 /* Advance n >= 0 time steps.  One step is, per node, the pull of the
  * post-collision populations of the neighbours (streaming, Eq. 2), half-way
- * bounce-back at the cylinder (Sec. 3.1), the boundary corrections of
+ * bounce-back at the cylinder (half-way, Sec. 3.1, or interpolated,
+ * Sec. 2.4), the boundary corrections of
  * Sec. 2.3 and the inlet, then the collision (BGK, Eqs. 2-4, or MRT, Eq. 6); the force on the
  * cylinder is taken by momentum exchange (Eq. 14) in the same pass.
  * Stream-ordered and asynchronous; a divergence is reported by the next

@@ -35,14 +35,14 @@ def splitmix64(seed: int):
         yield z ^ (z >> 31)
 
 
-def channel(d: int, u: float = 0.05, re: float = 100.0) -> dict:
-    """The 41 D x 21 D cylinder channel as keyword arguments."""
-    return dict(nx=41 * d, ny=21 * d, diameter=d, cx2=21 * d, cy2=21 * d, u_in=u, re=re)
-
-
 # diag(S) of Sec. 2.1; 0 in the two shear entries stands for 1/tau
 PAPER_RATES = (1.0, 1.1, 1.1, 1.0, 1.1, 1.0, 1.1, 0.0, 0.0)
 MRT = 1
+
+
+def channel(d: int, u: float = 0.05, re: float = 100.0) -> dict:
+    """The 41 D x 21 D cylinder channel as keyword arguments."""
+    return dict(nx=41 * d, ny=21 * d, diameter=d, cx2=21 * d, cy2=21 * d, u_in=u, re=re)
 
 
 def paper_channel(d: int = 20, u: float = 0.02, re: float = 100.0) -> dict:
@@ -67,15 +67,19 @@ def truncated_window(d: int = 40, u: float = 0.05, re: float = 100.0) -> dict:
     return dict(nx=26 * d, ny=11 * d, diameter=d, cx2=21 * d, cy2=11 * d, u_in=u, re=re)
 
 
-def ensemble(n: int = 64, seed: int = 2605, u: float = 0.05) -> list[dict]:
+def ensemble(n: int = 64, seed: int = 2605, u: float = 0.05, mrt: bool = False) -> list[dict]:
     """n cylinder channels with D = 8 + (r mod 25) and Re = 60 + 140 v, where r
-    and v (uniform in [0, 1)) come from SplitMix64."""
+    and v (uniform in [0, 1)) come from SplitMix64; tau from Re (0.506 to
+    0.54).  `mrt` selects the collision of Sec. 2.1 with its rates."""
     g = splitmix64(seed)
     cases = []
     for _ in range(n):
         d = 8 + next(g) % 25
         re = 60.0 + 140.0 * ((next(g) >> 11) * (1.0 / (1 << 53)))
-        cases.append(channel(int(d), u=u, re=re))
+        kw = channel(int(d), u=u, re=re)
+        if mrt:
+            kw.update(collision=MRT, s_rates=PAPER_RATES)
+        cases.append(kw)
     return cases
 
 

@@ -17,6 +17,7 @@ OK, ERR_INVALID_ARG, ERR_HIP, ERR_OOM, ERR_DIVERGED, ERR_RANGE, ERR_STATE = 0, -
 WALL_FREE_SLIP, WALL_PERIODIC, WALL_NEBB, WALL_MOVING_BB = 0, 1, 2, 3
 OUTLET_COPY_ALL, OUTLET_COPY_UNKNOWN = 0, 1
 COLLISION_BGK, COLLISION_MRT = 0, 1
+BOUNCE_HALFWAY, BOUNCE_INTERP = 0, 1
 
 
 class LbmError(RuntimeError):
@@ -55,6 +56,8 @@ class Params(ctypes.Structure):
         ("perturb_amp", ctypes.c_double),
         ("hist_capacity", ctypes.c_int64),
         ("s_rates", ctypes.c_double * 9),
+        ("bounce", ctypes.c_int32),
+        ("reserved1", ctypes.c_int32),
     ]
 
 
@@ -151,7 +154,8 @@ def check(status: int):
 def make_params(nx, ny, diameter=0, cx2=None, cy2=None, u_in=0.1, re=100.0, tau=0.0,
                 wall=WALL_FREE_SLIP, outlet_mode=OUTLET_COPY_ALL, u_wall_top=math.nan,
                 u_wall_bottom=math.nan, x_periodic=False, perturb_amp=1e-3,
-                hist_capacity=1 << 20, collision=COLLISION_BGK, s_rates=None) -> Params:
+                hist_capacity=1 << 20, collision=COLLISION_BGK, s_rates=None,
+                bounce=BOUNCE_HALFWAY) -> Params:
     """lbm_params from keywords; s_rates (9 values, MRT) defaults to the
     rates of Sec. 2.1, with 0 for the shear rates meaning 1/tau."""
     p = Params()
@@ -166,6 +170,7 @@ def make_params(nx, ny, diameter=0, cx2=None, cy2=None, u_in=0.1, re=100.0, tau=
     p.perturb_amp = perturb_amp
     p.hist_capacity = hist_capacity
     p.collision = collision
+    p.bounce = bounce
     if s_rates is not None:
         if len(s_rates) != 9:
             raise ValueError("s_rates needs 9 values")

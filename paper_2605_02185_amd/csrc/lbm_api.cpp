@@ -55,6 +55,26 @@ namespace lbm {
 
 lbm_status set_error(lbm_status s, const char* msg) { return fail(s, "%s", msg); }
 
+// Sec. 2.4, link-wise approach: the wall cuts the link from fluid node
+// (x, y) into the solid (along -c_k for pull direction k) at a fraction q of
+// its length.  With the disk's circle in doubled coordinates, X = 2x - cx2,
+// Y = 2y - cy2, the cut solves (X - 2q c_kx)^2 + (Y - 2q c_ky)^2 = D^2; its
+// smaller root lies in (0, 1].  Where q < 1/2 needs the fluid node on the
+// far side (x + c_k) and that node is not fluid, the link falls back to
+// q = 1/2 (half-way bounce-back).
+double link_fraction(const lbm_params& p, int x, int y, int k) {
+  const double X = 2.0 * x - p.cx2, Y = 2.0 * y - p.cy2, D = p.diameter;
+  const double dx = -CX[k], dy = -CY[k];
+  const double a = 4.0 * (dx * dx + dy * dy), b = 4.0 * (X * dx + Y * dy), c = X * X + Y * Y - D * D;
+  const double disc = std::max(0.0, b * b - 4.0 * a * c);
+  double q = (-b - std::sqrt(disc)) / (2.0 * a);
+  q = std::min(1.0, std::max(1e-12, q));
+  const int xb = x + CX[k], yb = y + CY[k];
+  const bool behind_fluid = xb >= 0 && xb < p.nx && yb >= 0 && yb < p.ny && !solid_at(p, xb, yb);
+  if (q < 0.5 && !behind_fluid) q = 0.5;
+  return q;
+}
+
 lbm_status build_geometry(const lbm_params* p, HostGeometry* out) {
   Geometry& g = out->g;
   g = Geometry{};
@@ -100,6 +120,18 @@ lbm_status build_geometry(const lbm_params* p, HostGeometry* out) {
           out->flags[(size_t)j * g.rw + i] = f;
           if (f >> 1) out->link_index[(size_t)j * g.rw + i] = g.n_link_nodes++;
         }
+      if (p->bounce == LBM_BOUNCE_INTERP) {
+        out->q.assign((size_t)g.n_link_nodes * 8, 0.5f);
+        for (int j = 0; j < g.rh; ++j)
+          for (int i = 0; i < g.rw; ++i) {
+            const int32_t idx = out->link_index[(size_t)j * g.rw + i];
+            if (idx < 0) continue;
+            const int x = g.rx0 + i, y = g.ry0 + j;
+            for (int k = 1; k < 9; ++k)
+              if ((out->flags[(size_t)j * g.rw + i] >> k) & 1)
+                out->q[(size_t)idx * 8 + k - 1] = (float)link_fraction(*p, x, y, k);
+          }
+      }
     }
   }
   return LBM_OK;
@@ -115,6 +147,7 @@ Physics make_physics(const lbm_params* p) {
   ph.outlet_mode = p->outlet_mode;
   ph.x_periodic = p->x_periodic;
   ph.mrt = p->collision == LBM_COLLISION_MRT;
+  ph.interp_bb = p->bounce == LBM_BOUNCE_INTERP && p->diameter > 0;
   auto rate = [&](int i) { return (float)(p->s_rates[i] > 0 ? p->s_rates[i] : 1.0 / lbm_params_tau(p)); };
   ph.s_e = rate(1);
   ph.s_eps = rate(2);
@@ -149,6 +182,7 @@ struct lbm_ctx {
   int cur = 0;
   uint16_t* d_flags = nullptr;
   int32_t* d_link_index = nullptr;
+  float* d_q = nullptr;
   double2* d_partials = nullptr;
   // two-step variants: segments that need the boundary code (seg * ntx + strip)
   int* d_gen = nullptr;
@@ -213,6 +247,8 @@ lbm_status lbm_validate_params(const lbm_params* p) {
   if (p->x_periodic != 0 && p->x_periodic != 1) return fail(LBM_ERR_INVALID_ARG, "x_periodic must be 0 or 1");
   if (p->collision != LBM_COLLISION_BGK && p->collision != LBM_COLLISION_MRT)
     return fail(LBM_ERR_INVALID_ARG, "unknown collision %d", p->collision);
+  if (p->bounce != LBM_BOUNCE_HALFWAY && p->bounce != LBM_BOUNCE_INTERP)
+    return fail(LBM_ERR_INVALID_ARG, "unknown bounce-back mode %d", p->bounce);
   if (p->collision == LBM_COLLISION_MRT)
     for (int i : {1, 2, 4, 6, 7, 8}) {
       const double s = p->s_rates[i];
@@ -331,6 +367,7 @@ void free_ctx(lbm_ctx* c) {
   (void)hipFree(c->buf[1]);
   (void)hipFree(c->d_flags);
   (void)hipFree(c->d_link_index);
+  (void)hipFree(c->d_q);
   (void)hipFree(c->d_partials);
   (void)hipFree(c->d_gen);
   (void)hipFree(c->d_hist);
@@ -408,8 +445,13 @@ lbm_status lbm_create(const lbm_params* p, void* stream, lbm_ctx** out) {
     CREATE_TRY(hipMemcpyAsync(c->d_link_index, link_index.data(), link_index.size() * sizeof(int32_t),
                               hipMemcpyHostToDevice, c->stream));
   }
+  if (!hg.q.empty()) {
+    CREATE_TRY(hipMalloc(&c->d_q, hg.q.size() * sizeof(float)));
+    CREATE_TRY(hipMemcpyAsync(c->d_q, hg.q.data(), hg.q.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  }
   g.flags = c->d_flags;
   g.link_index = c->d_link_index;
+  g.q = c->d_q;
   {
     const size_t bytes = sizeof(double2) * (size_t)slots_of(c) * lbm::kRing;
     CREATE_TRY(hipMalloc(&c->d_partials, bytes));

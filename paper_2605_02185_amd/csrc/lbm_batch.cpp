@@ -210,6 +210,13 @@ lbm_status create_impl(const lbm_params* cases, const int64_t* budgets, int32_t 
                           hipMemcpyHostToDevice, b->stream));
       c.g.flags = fl;
       c.g.link_index = li;
+      if (!b->hg[k].q.empty()) {
+        float* q = nullptr;
+        if ((st = dmalloc(b, (void**)&q, b->hg[k].q.size() * sizeof(float))) != LBM_OK) return st;
+        BTRY(hipMemcpyAsync(q, b->hg[k].q.data(), b->hg[k].q.size() * sizeof(float), hipMemcpyHostToDevice,
+                            b->stream));
+        c.g.q = q;
+      }
     }
     c.partial = partials + link_off[k];
     c.hist_cap = p.hist_capacity;

@@ -38,6 +38,10 @@ struct Geometry {
   // force contribution goes, so the sum order never depends on the tiling
   const int32_t* link_index;
   int n_link_nodes;
+  // interpolated bounce-back: wall fraction q of the link of pull direction
+  // k (1..8) of link node i at q[8 i + k - 1] (the link from the node along
+  // -c_k ends in the solid); null with half-way bounce-back
+  const float* q;
 };
 
 struct Physics {
@@ -46,6 +50,7 @@ struct Physics {
   float u_top, u_bot;
   int wall, outlet_mode, x_periodic;
   int mrt;         // 1: Eq. 6 with the rates below instead of Eq. 2
+  int interp_bb;   // 1: interpolated bounce-back on the cylinder (Geometry::q)
   float s_e, s_eps, s_qx, s_qy, s_pxx, s_pxy;  // rates of the non-conserved moments
 };
 
@@ -173,6 +178,7 @@ struct HostGeometry {
   Geometry g;                       // device pointers left null
   std::vector<uint16_t> flags;      // [rh][rw]
   std::vector<int32_t> link_index;  // [rh][rw]
+  std::vector<float> q;             // [n_link_nodes][8], interpolated bounce-back only
 };
 lbm_status build_geometry(const lbm_params* p, HostGeometry* out);
 Physics make_physics(const lbm_params* p);

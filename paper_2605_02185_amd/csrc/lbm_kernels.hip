@@ -156,8 +156,32 @@ __device__ __forceinline__ float load(const float* __restrict__ A, const Geometr
   return A[(uint32_t)k * (uint32_t)g.plane + (uint32_t)y * (uint32_t)g.pitch + (uint32_t)x];
 }
 
+// Interpolated bounce-back (Sec. 2.4; the linear scheme of Bouzidi,
+// Firdaouss & Lallemand) for the population arriving along c_k at a fluid
+// node whose neighbour x - c_k is solid, the wall cutting that link at the
+// fraction q: fo = f*_opp(k)(x) (what left towards the wall), fb =
+// f*_opp(k)(x + c_k) (the same population one node further from the wall),
+// fk = f*_k(x).  q < 1/2 interpolates 2q fo + (1 - 2q) fb, q >= 1/2
+// interpolates fo / (2q) + (1 - 1/(2q)) fk; both give fo at q = 1/2.  The
+// weights sum to one and opposite directions share a weight, so the same
+// formula holds on the stored deviations f - w.
+__device__ __forceinline__ float bfl(float q, float fo, float fb, float fk) {
+#pragma clang fp contract(off)
+  if (q < 0.5f) {
+    const float t = 2.0f * q;
+    return __fmaf_rn(t, fo, (1.0f - t) * fb);
+  }
+  const float r = 0.5f / q;
+  return __fmaf_rn(r, fo, (1.0f - r) * fk);
+}
+
+__device__ __forceinline__ int link_slot(const Geometry& geo, int x, int y) {
+  return geo.link_index[(y - geo.ry0) * geo.rw + (x - geo.rx0)];
+}
+
 // Streamed populations of node (x, y): pull with the wrap-arounds of the
-// periodic modes and half-way bounce-back on the cylinder.  Populations
+// periodic modes and bounce-back on the cylinder (half-way, or interpolated
+// with the links' wall fractions).  Populations
 // whose source lies outside the lattice are the missing ones of Fig. 2; they
 // are set to 0 here and overwritten by the boundary corrections.
 __device__ __forceinline__ void pull(const StepArgs& a, int x, int y, uint16_t fl, float (&g)[9]) {
@@ -165,7 +189,16 @@ __device__ __forceinline__ void pull(const StepArgs& a, int x, int y, uint16_t f
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     if (k > 0 && ((fl >> k) & 1)) {
-      g[k] = load(a.A, a.g, OPP[k], x, y);
+      const float fo = load(a.A, a.g, OPP[k], x, y);
+      if (a.p.interp_bb) {
+        const float q = a.g.q[8 * link_slot(a.g, x, y) + k - 1];
+        // the cylinder keeps two nodes from every edge: x + c_k is inside
+        const float fb = q < 0.5f ? load(a.A, a.g, OPP[k], x + CX[k], y + CY[k]) : 0.0f;
+        const float fk = q < 0.5f ? 0.0f : load(a.A, a.g, k, x, y);
+        g[k] = bfl(q, fo, fb, fk);
+      } else {
+        g[k] = fo;
+      }
       continue;
     }
     int sx = x - CX[k], sy = y - CY[k];
@@ -250,21 +283,30 @@ __device__ __forceinline__ void inlet_bc(const Physics& p, bool corner, float (&
   }
 }
 
-// Eq. 14: each bounced population g_k = f*_opp(k)(x) left along c_opp(k)
-// and came back along c_k, giving the body 2 c_opp(k) f*_opp(k).  Written to
-// the node's fixed slot of this step's contributions.
+// Eq. 14: on each link the population f*_opp(k)(x) left along c_opp(k) and
+// g_k came back along c_k, giving the body (f*_opp(k) + g_k) c_opp(k); with
+// half-way bounce-back both are f*_opp(k): 2 c_opp(k) g_k.  `own` holds the
+// node's post-collision f* (read only with interpolated bounce-back).
+// Written to the node's fixed slot of this step's contributions.
 __device__ __forceinline__ void link_force(const Geometry& geo, double2* __restrict__ partial, int x, int y,
-                                           uint16_t fl, const float (&g)[9]) {
+                                           uint16_t fl, const float (&g)[9], const float (&own)[9],
+                                           bool interp) {
   double Fx = 0.0, Fy = 0.0;
 #pragma unroll
   for (int k = 1; k < 9; ++k)
     if ((fl >> k) & 1) {
-      const double fk = (double)g[k] + (k < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
-      Fx -= 2.0 * (double)CX[k] * fk;
-      Fy -= 2.0 * (double)CY[k] * fk;
+      const double w = k < 5 ? 1.0 / 9.0 : 1.0 / 36.0;
+      if (interp) {
+        const double sum = ((double)own[OPP[k]] + w) + ((double)g[k] + w);
+        Fx -= (double)CX[k] * sum;
+        Fy -= (double)CY[k] * sum;
+      } else {
+        const double fk = (double)g[k] + w;
+        Fx -= 2.0 * (double)CX[k] * fk;
+        Fy -= 2.0 * (double)CY[k] * fk;
+      }
     }
-  const int idx = geo.link_index[(y - geo.ry0) * geo.rw + (x - geo.rx0)];
-  partial[idx] = make_double2(Fx, Fy);
+  partial[link_slot(geo, x, y)] = make_double2(Fx, Fy);
 }
 
 // Learned-closure residuals (when enabled) on the three missing populations
@@ -347,7 +389,14 @@ __device__ __forceinline__ void general_update(const StepArgs& a, int x, int y, 
     gather(a, x, y, fl, g);
   }
   if (open_x && x == 0) inlet_bc(a.p, corner_y, g);
-  if ((fl >> 1) && owner) link_force(a.g, a.partial, x, y, fl, g);
+  if ((fl >> 1) && owner) {
+    float own[9];
+    if (a.p.interp_bb) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) own[k] = load(a.A, a.g, k, x, y);
+    }
+    link_force(a.g, a.partial, x, y, fl, g, own, a.p.interp_bb);
+  }
   collide(g, a.p, out, bad);
 }
 
@@ -621,11 +670,31 @@ __device__ __forceinline__ void second_update(const StepArgs& a, int x, int y, b
   const bool outlet = active && open_x && x == nx - 1;
   const bool corner_y = a.p.wall != kWallPeriodic && (y == 0 || y == ny - 1);
   const uint16_t fl = active ? node_flags(a.g, x, y) : 0;
+  // interpolated bounce-back needs f*_opp(k) at x + c_k: the neighbouring
+  // row and lane (wave-wide moves, only where the wave has links)
+  float bh[9];
+  const bool interp = a.p.interp_bb && __any(fl >> 1);
+  if (interp) {
+    bh[0] = 0.0f;
+    bh[1] = from_right(w1[3]);
+    bh[2] = w2[4];
+    bh[3] = from_left(w1[1]);
+    bh[4] = w0[2];
+    bh[5] = from_right(w2[7]);
+    bh[6] = from_left(w2[8]);
+    bh[7] = from_left(w0[5]);
+    bh[8] = from_right(w0[6]);
+  }
   float g[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    if (k > 0 && ((fl >> k) & 1)) {  // half-way bounce-back on the cylinder
-      g[k] = w1[OPP[k]];
+    if (k > 0 && ((fl >> k) & 1)) {  // bounce-back on the cylinder
+      if (interp) {
+        const float q = a.g.q[8 * link_slot(a.g, x, y) + k - 1];
+        g[k] = bfl(q, w1[OPP[k]], bh[k], w1[k]);
+      } else {
+        g[k] = w1[OPP[k]];
+      }
       continue;
     }
     int sx = x - CX[k], sy = y - CY[k];
@@ -663,7 +732,7 @@ __device__ __forceinline__ void second_update(const StepArgs& a, int x, int y, b
     return;
   }
   if (open_x && x == 0) inlet_bc(a.p, corner_y, g);
-  if ((fl >> 1) && owner) link_force(a.g, a.partial2, x, y, fl, g);
+  if ((fl >> 1) && owner) link_force(a.g, a.partial2, x, y, fl, g, w1, a.p.interp_bb);
   collide(g, a.p, out, b);
   bad |= b && owner;
 }

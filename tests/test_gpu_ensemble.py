@@ -54,10 +54,11 @@ def test_mixed_ensemble_matches_separate_runs_bitwise():
             assert np.array_equal(a, c), i
 
 
-def test_full_ensemble_of_64_channels_matches_separate_runs():
-    """The 64-case ensemble (D in 8..32, Re in [60, 200], U = 0.05): 130 steps
-    together, then every case checked against its own run."""
-    cases = ensemble()
+@pytest.mark.parametrize("mrt", [False, True])
+def test_full_ensemble_of_64_channels_matches_separate_runs(mrt):
+    """The 64-case ensemble (D in 8..32, Re in [60, 200], U = 0.05, tau from
+    Re): 130 steps together, then every case checked against its own run."""
+    cases = ensemble(mrt=mrt)
     ens = lbm.Ensemble([lbm.make_params(**kw) for kw in cases])
     ens.step(130)
     ens.sync()
@@ -94,3 +95,19 @@ def test_autotuner_picks_a_variant_and_caches_it(tmp_path):
     best = lat.autotune(10, cache)
     assert 1 <= best <= lbm.num_variants()
     assert len(open(cache).read().split()) == 4
+
+
+def test_ensemble_at_the_reynolds_tau_needs_mrt():
+    """tau = 3 U D / Re + 1/2 spans 0.507-0.56 over the 64 cases: with BGK
+    most of them blow up within a few thousand steps, with the MRT rates of
+    Sec. 2.1 none does (the paper's reason for MRT)."""
+    out = {}
+    for mrt in (False, True):
+        cases = ensemble(mrt=mrt)
+        ens = lbm.Ensemble([lbm.make_params(**kw) for kw in cases])
+        ens.step(4000)
+        out[mrt] = sum(1 for i in range(len(cases)) if ens.info(i)[1])
+        ens.close()
+    note(f"  diverged cases in 4000 steps: BGK {out[False]}, MRT {out[True]}")
+    assert out[True] == 0
+    assert out[False] >= 32

@@ -99,3 +99,21 @@ def test_e2_window_statistics_match_the_oracle():
     """1600 x 800: 500k GPU steps, then three periods (36k steps) on both."""
     window_parity(dict(WORKLOADS["cyl_d40_mrt"]), spin_up=500000, window=36000, periods=2,
                   require_established=False)
+
+
+@pytest.mark.timeout(300)
+def test_interpolated_bounce_back_is_grid_independent():
+    """Sec. 2.4's link-wise (interpolated) bounce-back on the paper's two
+    lattices: mean drag at D = 20 and D = 40 agree within 1.5 %, where the
+    staircase half-way bounce-back moves it by 5 %; at D = 20 it lands on the
+    paper's Table 2 values (1.4, 0.31, 0.168) within 3 %, 5 % and 1 %."""
+    res = {}
+    for bounce in (lbm.BOUNCE_HALFWAY, lbm.BOUNCE_INTERP):
+        res[bounce] = (_stats(dict(WORKLOADS["cyl_d20_mrt"], bounce=bounce), 300000, 50000),
+                       _stats(dict(WORKLOADS["cyl_d40_mrt"], bounce=bounce), 700000, 100000))
+    (hw20, hw40), (bz20, bz40) = res[lbm.BOUNCE_HALFWAY], res[lbm.BOUNCE_INTERP]
+    assert abs(bz20["mean_cd"] / bz40["mean_cd"] - 1) < 0.015
+    assert abs(hw20["mean_cd"] / hw40["mean_cd"] - 1) > 0.03
+    assert abs(bz20["mean_cd"] / 1.4 - 1) < 0.03
+    assert abs(bz20["cl_amp"] / 0.31 - 1) < 0.05
+    assert abs(bz20["st"] / 0.168 - 1) < 0.01
