@@ -23,7 +23,7 @@ _LIB_PATH = os.path.join(_HERE, "liblbm_oracle.so")
 
 WALL_FREE_SLIP, WALL_PERIODIC, WALL_NEBB, WALL_MOVING_BB = 0, 1, 2, 3
 BGK, MRT = 0, 1
-BB_HALFWAY, BB_INTERP = 0, 1
+BB_HALFWAY, BB_INTERP, BB_FULLWAY = 0, 1, 2
 # Relaxation rates of the paper's MRT (Sec. 2.1); the last two (shear) are 1/tau.
 PAPER_S = (1.0, 1.1, 1.1, 1.0, 1.1, 1.0, 1.1, 0.0, 0.0)
 OUTLET_COPY_ALL, OUTLET_COPY_UNKNOWN = 0, 1

@@ -144,13 +144,18 @@ long oracle_digitise(const oracle_params* p, unsigned char* solid) {
   return count;
 }
 
+/* With full-way bounce-back the solid nodes carry populations; they start
+ * at rest, f = w (which their reversal leaves unchanged). */
 static void init_equilibrium(oracle* o) {
   const double U = o->p.u_in, a = o->p.perturb_amp;
   const double pi = 3.14159265358979323846;
   for (int y = 0; y < o->ny; ++y) {
     double v = o->ny > 1 ? a * U * sin(2.0 * pi * y / (o->ny - 1)) : 0.0;
-    for (int x = 0; x < o->nx; ++x)
-      for (int k = 0; k < 9; ++k) o->f[node(o, x, y) * 9 + k] = feq(k, 1.0, U, v);
+    for (int x = 0; x < o->nx; ++x) {
+      size_t n = node(o, x, y);
+      int rest = o->p.bounce == ORACLE_BB_FULLWAY && o->solid[n];
+      for (int k = 0; k < 9; ++k) o->f[n * 9 + k] = rest ? W[k] : feq(k, 1.0, U, v);
+    }
   }
 }
 
@@ -238,7 +243,9 @@ static int collide(oracle* o) {
       const double* fn = o->f + n * 9;
       double* out = o->fs + n * 9;
       if (o->solid[n]) {
-        for (int k = 0; k < 9; ++k) out[k] = fn[k];
+        /* full-way bounce-back: the populations that arrived are sent back */
+        int full = o->p.bounce == ORACLE_BB_FULLWAY;
+        for (int k = 0; k < 9; ++k) out[k] = full ? fn[OPP[k]] : fn[k];
         o->rho_t[n] = 1.0;
         continue;
       }
@@ -388,7 +395,9 @@ static double bounced(const oracle* o, int x, int y, int k, double q) {
 /* O2: Eq. 14 summed over the links: the population leaving along c_k is
  * f*_k (in), the one coming back along -c_k is the bounced value (out), and
  * the body receives (f_in + f_out) c_k.  With half-way bounce-back both are
- * f*_k (stationary wall, same step): 2 c_k f*_k. */
+ * f*_k (stationary wall, same step): 2 c_k f*_k.  With full-way bounce-back
+ * f*_k reaches the solid node in this step and leaves it reversed in the
+ * next: the same 2 c_k f*_k, booked at this step. */
 static void force(const oracle* o, double* fx, double* fy) {
   double sx = 0.0, sy = 0.0;
   for (long i = 0; i < o->n_links; ++i) {
@@ -409,7 +418,10 @@ static void force(const oracle* o, double* fx, double* fy) {
 }
 
 /* O3: push streaming with bounce-back (half-way or interpolated) at solid
- * nodes. */
+ * nodes; with full-way bounce-back (Sec. 3.1) solid nodes take part in the
+ * streaming like fluid ones and reverse what arrived in their collision, so
+ * a population that reaches the wall returns to its fluid node one step
+ * later. */
 static void stream(oracle* o) {
   long total = (long)o->nx * o->ny * 9;
 #pragma omp parallel for schedule(static)
@@ -418,12 +430,13 @@ static void stream(oracle* o) {
   for (int y = 0; y < o->ny; ++y)
     for (int x = 0; x < o->nx; ++x) {
       size_t n = node(o, x, y);
-      if (o->solid[n]) continue;
+      int full = o->p.bounce == ORACLE_BB_FULLWAY;
+      if (o->solid[n] && !full) continue;
       for (int k = 0; k < 9; ++k) {
         int xn, yn;
         if (!neighbour(o, x, y, k, &xn, &yn)) continue; /* leaves the lattice */
         size_t m = node(o, xn, yn);
-        if (o->solid[m])
+        if (o->solid[m] && !full)
           o->g[n * 9 + OPP[k]] = o->node_q ? bounced(o, x, y, k, o->node_q[n * 9 + k]) : o->fs[n * 9 + k];
         else
           o->g[m * 9 + k] = o->fs[n * 9 + k];
@@ -547,7 +560,7 @@ long oracle_step(oracle* o, long nsteps, double* fx, double* fy) {
     long nn = (long)o->nx * o->ny;
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (long n = 0; n < nn; ++n) {
-      if (o->solid[n]) continue;
+      if (o->solid[n] && o->p.bounce != ORACLE_BB_FULLWAY) continue;
       for (int k = 0; k < 9; ++k) {
         double v = o->g[n * 9 + k];
         if (!isfinite(v)) bad = 1;

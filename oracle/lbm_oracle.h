@@ -37,7 +37,7 @@ enum { ORACLE_OUTLET_COPY_ALL = 0, ORACLE_OUTLET_COPY_UNKNOWN = 1 };
 
 enum { ORACLE_BGK = 0, ORACLE_MRT = 1 };
 
-enum { ORACLE_BB_HALFWAY = 0, ORACLE_BB_INTERP = 1 };
+enum { ORACLE_BB_HALFWAY = 0, ORACLE_BB_INTERP = 1, ORACLE_BB_FULLWAY = 2 };
 
 typedef struct {
   int nx, ny;             /* lattice nodes x in [0,nx), y in [0,ny) */
@@ -55,7 +55,8 @@ typedef struct {
   double gx, gy;          /* body-force acceleration (Guo forcing), test boxes only */
   int collision;          /* ORACLE_BGK (Eq. 2) or ORACLE_MRT (Eq. 6) */
   double s_rates[9];      /* MRT relaxation rates diag(S); entries 7 and 8 <= 0 mean 1/tau */
-  int bounce;             /* cylinder links: ORACLE_BB_HALFWAY or ORACLE_BB_INTERP (Sec. 2.4) */
+  int bounce;             /* cylinder: ORACLE_BB_HALFWAY, ORACLE_BB_INTERP (Sec. 2.4) or
+                           * ORACLE_BB_FULLWAY (Sec. 3.1) */
   double q_fixed;         /* interpolated links: > 0 gives every link this wall fraction
                            * (test geometries); else q from the circle of the disk, or 1/2
                            * when the caller supplies the solid mask */
