@@ -243,9 +243,10 @@ static int collide(oracle* o) {
       const double* fn = o->f + n * 9;
       double* out = o->fs + n * 9;
       if (o->solid[n]) {
-        /* full-way bounce-back: the populations that arrived are sent back */
-        int full = o->p.bounce == ORACLE_BB_FULLWAY;
-        for (int k = 0; k < 9; ++k) out[k] = full ? fn[OPP[k]] : fn[k];
+        /* full-way bounce-back: the populations that arrived are sent back
+         * (a state given as post-collision is already reversed) */
+        int reverse = o->p.bounce == ORACLE_BB_FULLWAY && !o->state_is_post;
+        for (int k = 0; k < 9; ++k) out[k] = reverse ? fn[OPP[k]] : fn[k];
         o->rho_t[n] = 1.0;
         continue;
       }

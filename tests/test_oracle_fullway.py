@@ -48,7 +48,8 @@ def _wall_links(solid):
 def test_population_comes_back_one_step_later():
     """f*_k(x) sent towards the solid node x + c_k sits there in slot k after
     one step, leaves reversed, and is f_opp(k)(x) after the second step; with
-    half-way bounce-back it is f_opp(k)(x) after the first."""
+    half-way bounce-back it is f_opp(k)(x) after the first.  What the solid
+    node held in the given (post-collision) state is what reaches x first."""
     p = OracleParams(**BOX, bounce=BB_FULLWAY)
     solid = digitise(p)
     links = _wall_links(solid)
@@ -62,6 +63,9 @@ def test_population_comes_back_one_step_later():
     f2 = o.get_f()
     for k, sx, sy, x, y in links:
         assert f1[k, sy, sx] == f0[k, y, x]
+        # the given state is post-collision at the solid nodes too: it
+        # streams out unchanged in the first step
+        assert f1[OPP[k], y, x] == f0[OPP[k], sy, sx]
         assert fs1[OPP[k], sy, sx] == f1[k, sy, sx]
         assert f2[OPP[k], y, x] == f0[k, y, x]
 
