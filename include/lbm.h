@@ -60,8 +60,13 @@ typedef enum {
 /* Cylinder wall treatment (Sec. 2.4). */
 typedef enum {
   LBM_BOUNCE_HALFWAY = 0, /* half-way bounce-back on the staircase disk (the paper's choice) */
-  LBM_BOUNCE_INTERP = 1   /* link-wise interpolated bounce-back (Bouzidi, Firdaouss & Lallemand)
+  LBM_BOUNCE_INTERP = 1,  /* link-wise interpolated bounce-back (Bouzidi, Firdaouss & Lallemand)
                            * with the wall fraction q of each link from the circle */
+  LBM_BOUNCE_FULLWAY = 2  /* full-way bounce-back (Sec. 3.1): solid nodes stream like fluid ones
+                           * and their collision reverses every population, so what reaches the
+                           * wall returns to its fluid node one step later; solid nodes start at
+                           * rest (f = w) and the momentum of each link is booked in the step
+                           * its population enters the wall */
 } lbm_bounce;
 
 /* Collision operator. */
@@ -130,9 +135,9 @@ lbm_status lbm_create(const lbm_params* p, void* stream, lbm_ctx** out);
 void lbm_destroy(lbm_ctx* ctx);
 
 /* Advance n >= 0 time steps.  One step is, per node, the pull of the
- * post-collision populations of the neighbours (streaming, Eq. 2), half-way
- * bounce-back at the cylinder (half-way, Sec. 3.1, or interpolated,
- * Sec. 2.4), the boundary corrections of
+ * post-collision populations of the neighbours (streaming, Eq. 2),
+ * bounce-back at the cylinder (half-way or full-way, Sec. 3.1, or
+ * interpolated, Sec. 2.4), the boundary corrections of
  * Sec. 2.3 and the inlet, then the collision (BGK, Eqs. 2-4, or MRT, Eq. 6); the force on the
  * cylinder is taken by momentum exchange (Eq. 14) in the same pass.
  * Stream-ordered and asynchronous; a divergence is reported by the next

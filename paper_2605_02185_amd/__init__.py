@@ -15,6 +15,7 @@ from . import _lib
 from ._lib import (
     BOUNCE_HALFWAY,
     BOUNCE_INTERP,
+    BOUNCE_FULLWAY,
     COLLISION_BGK,
     COLLISION_MRT,
     OUTLET_COPY_ALL,
@@ -34,7 +35,7 @@ __all__ = [
     "Lattice", "Ensemble", "Mlp", "column_moments", "make_params", "MLP_PARAMS", "validate", "tau_of", "geometry", "shedding_stats", "copy_probe",
     "num_variants", "variant_name", "LbmError", "DivergedError", "RangeError",
     "WALL_FREE_SLIP", "WALL_PERIODIC", "WALL_NEBB", "WALL_MOVING_BB",
-    "OUTLET_COPY_ALL", "OUTLET_COPY_UNKNOWN", "COLLISION_BGK", "COLLISION_MRT", "BOUNCE_HALFWAY", "BOUNCE_INTERP",
+    "OUTLET_COPY_ALL", "OUTLET_COPY_UNKNOWN", "COLLISION_BGK", "COLLISION_MRT", "BOUNCE_HALFWAY", "BOUNCE_INTERP", "BOUNCE_FULLWAY",
 ]
 
 

@@ -17,7 +17,7 @@ OK, ERR_INVALID_ARG, ERR_HIP, ERR_OOM, ERR_DIVERGED, ERR_RANGE, ERR_STATE = 0, -
 WALL_FREE_SLIP, WALL_PERIODIC, WALL_NEBB, WALL_MOVING_BB = 0, 1, 2, 3
 OUTLET_COPY_ALL, OUTLET_COPY_UNKNOWN = 0, 1
 COLLISION_BGK, COLLISION_MRT = 0, 1
-BOUNCE_HALFWAY, BOUNCE_INTERP = 0, 1
+BOUNCE_HALFWAY, BOUNCE_INTERP, BOUNCE_FULLWAY = 0, 1, 2
 
 
 class LbmError(RuntimeError):

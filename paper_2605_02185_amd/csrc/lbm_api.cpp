@@ -148,6 +148,7 @@ Physics make_physics(const lbm_params* p) {
   ph.x_periodic = p->x_periodic;
   ph.mrt = p->collision == LBM_COLLISION_MRT;
   ph.interp_bb = p->bounce == LBM_BOUNCE_INTERP && p->diameter > 0;
+  ph.full_bb = p->bounce == LBM_BOUNCE_FULLWAY && p->diameter > 0;
   auto rate = [&](int i) { return (float)(p->s_rates[i] > 0 ? p->s_rates[i] : 1.0 / lbm_params_tau(p)); };
   ph.s_e = rate(1);
   ph.s_eps = rate(2);
@@ -247,7 +248,7 @@ lbm_status lbm_validate_params(const lbm_params* p) {
   if (p->x_periodic != 0 && p->x_periodic != 1) return fail(LBM_ERR_INVALID_ARG, "x_periodic must be 0 or 1");
   if (p->collision != LBM_COLLISION_BGK && p->collision != LBM_COLLISION_MRT)
     return fail(LBM_ERR_INVALID_ARG, "unknown collision %d", p->collision);
-  if (p->bounce != LBM_BOUNCE_HALFWAY && p->bounce != LBM_BOUNCE_INTERP)
+  if (p->bounce != LBM_BOUNCE_HALFWAY && p->bounce != LBM_BOUNCE_INTERP && p->bounce != LBM_BOUNCE_FULLWAY)
     return fail(LBM_ERR_INVALID_ARG, "unknown bounce-back mode %d", p->bounce);
   if (p->collision == LBM_COLLISION_MRT)
     for (int i : {1, 2, 4, 6, 7, 8}) {
@@ -466,7 +467,8 @@ lbm_status lbm_create(const lbm_params* p, void* stream, lbm_ctx** out) {
   CREATE_TRY(hipMemsetAsync(c->d_step, 0, sizeof(int64_t), c->stream));
   CREATE_TRY(hipMemsetAsync(c->d_bad_step, 0, sizeof(int64_t), c->stream));
   CREATE_TRY(lbm::launch_fill_int(c->d_bad, INT_MAX, c->stream));
-  CREATE_TRY(lbm::launch_init_equilibrium(c->buf[0], g, p->u_in, p->perturb_amp, c->stream));
+  CREATE_TRY(lbm::launch_init_equilibrium(c->buf[0], g, p->u_in, p->perturb_amp, c->phys.full_bb != 0,
+                                          c->stream));
   CREATE_TRY(hipStreamSynchronize(c->stream));
 #undef CREATE_TRY
   *out = c;

@@ -228,7 +228,7 @@ lbm_status create_impl(const lbm_params* cases, const int64_t* budgets, int32_t 
     BTRY(hipMemsetAsync(c.dev_step, 0, sizeof(int64_t), b->stream));
     BTRY(hipMemsetAsync(c.bad_step, 0, sizeof(int64_t), b->stream));
     BTRY(lbm::launch_fill_int(c.bad, INT_MAX, b->stream));
-    BTRY(lbm::launch_init_equilibrium(c.buf[0], c.g, p.u_in, p.perturb_amp, b->stream));
+    BTRY(lbm::launch_init_equilibrium(c.buf[0], c.g, p.u_in, p.perturb_amp, c.p.full_bb != 0, b->stream));
   }
   for (int v = 1; v <= lbm::num_variants(); ++v) {
     size_t total = 0;

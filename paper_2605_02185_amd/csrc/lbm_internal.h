@@ -22,7 +22,9 @@ constexpr int kRing = 64;
 
 // Node flags inside the cylinder rectangle: bit 0 = solid node; bit k
 // (k = 1..8) = the pull source x - c_k of this fluid node is solid, so
-// population k arrives by half-way bounce-back instead of streaming.
+// population k arrives by half-way (or interpolated) bounce-back instead of
+// streaming.  With full-way bounce-back the bits only mark the links whose
+// momentum the node books; every population streams.
 constexpr uint16_t kSolid = 1;
 
 struct Geometry {
@@ -51,6 +53,7 @@ struct Physics {
   int wall, outlet_mode, x_periodic;
   int mrt;         // 1: Eq. 6 with the rates below instead of Eq. 2
   int interp_bb;   // 1: interpolated bounce-back on the cylinder (Geometry::q)
+  int full_bb;     // 1: full-way bounce-back: solid nodes stream and reverse
   float s_e, s_eps, s_qx, s_qy, s_pxx, s_pxy;  // rates of the non-conserved moments
 };
 
@@ -135,7 +138,7 @@ hipError_t launch_force_reduce_batch(const CaseArgs* cases, int ncases, int coun
 hipError_t launch_force_reduce(const double2* partials, int nnodes, int count, double* hist,
                                int64_t cap, int64_t* dev_step, int* bad, int64_t* bad_step,
                                hipStream_t s);
-hipError_t launch_init_equilibrium(float* f, const Geometry& g, double u, double amp,
+hipError_t launch_init_equilibrium(float* f, const Geometry& g, double u, double amp, bool rest_solid,
                                    hipStream_t s);
 hipError_t launch_fields(const float* f, const Geometry& g, float* rho, float* ux, float* uy,
                          hipStream_t s);

@@ -181,14 +181,15 @@ __device__ __forceinline__ int link_slot(const Geometry& geo, int x, int y) {
 
 // Streamed populations of node (x, y): pull with the wrap-arounds of the
 // periodic modes and bounce-back on the cylinder (half-way, or interpolated
-// with the links' wall fractions).  Populations
+// with the links' wall fractions; with full-way bounce-back the solid
+// neighbour's reversed populations stream in like any other).  Populations
 // whose source lies outside the lattice are the missing ones of Fig. 2; they
 // are set to 0 here and overwritten by the boundary corrections.
 __device__ __forceinline__ void pull(const StepArgs& a, int x, int y, uint16_t fl, float (&g)[9]) {
   const int nx = a.g.nx, ny = a.g.ny;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    if (k > 0 && ((fl >> k) & 1)) {
+    if (k > 0 && ((fl >> k) & 1) && !a.p.full_bb) {
       const float fo = load(a.A, a.g, OPP[k], x, y);
       if (a.p.interp_bb) {
         const float q = a.g.q[8 * link_slot(a.g, x, y) + k - 1];
@@ -212,49 +213,50 @@ __device__ __forceinline__ void pull(const StepArgs& a, int x, int y, uint16_t f
 // populations g of one node; fs are the node's own post-collision
 // populations f*(t), read only by the moving-wall treatment.
 __device__ __forceinline__ void wall_bc(const Physics& p, bool top, const float (&fs)[9], float (&g)[9]) {
+  // Both rows are written with selects: as two branches the compiler merges
+  // them into run-time indexing of g, which moves g to scratch memory.  With
+  // sg = +1 on the top row and -1 on the bottom row the sign flips are exact,
+  // so each row gets the same arithmetic as its own formula.
+  const float sg = top ? 1.0f : -1.0f;
   switch (p.wall) {
-    case kWallFreeSlip:  // Eq. 7: specular reflection at the node
-      if (top) {
-        g[4] = g[2];
-        g[7] = g[6];
-        g[8] = g[5];
-      } else {
-        g[2] = g[4];
-        g[6] = g[7];
-        g[5] = g[8];
-      }
+    case kWallFreeSlip: {  // Eq. 7: specular reflection at the node
+      const float a2 = g[2], a4 = g[4], a5 = g[5], a6 = g[6], a7 = g[7], a8 = g[8];
+      g[4] = top ? a2 : a4;  // top: S, SW, SE from N, NW, NE
+      g[7] = top ? a6 : a7;
+      g[8] = top ? a5 : a8;
+      g[2] = top ? a2 : a4;  // bottom: N, NW, NE from S, SW, SE
+      g[6] = top ? a6 : a7;
+      g[5] = top ? a5 : a8;
       break;
+    }
     case kWallNebb: {  // Eqs. 9-10: wall density from the known populations
       const float U = top ? p.u_top : p.u_bot;
       const float d13 = 0.5f * (g[1] - g[3]);
-      if (top) {
-        const float rw = 1.0f + ((g[0] + g[1] + g[3]) + 2.0f * (g[2] + g[5] + g[6]));
-        const float m = 0.5f * rw * U;
-        g[4] = g[2];
-        g[7] = g[5] + d13 - m;
-        g[8] = g[6] - d13 + m;
-      } else {
-        const float rw = 1.0f + ((g[0] + g[1] + g[3]) + 2.0f * (g[4] + g[7] + g[8]));
-        const float m = 0.5f * rw * U;
-        g[2] = g[4];
-        g[5] = g[7] - d13 + m;
-        g[6] = g[8] + d13 - m;
-      }
+      // the populations leaving through the wall: N, NE, NW (top), S, SW, SE (bottom)
+      const float k0 = top ? g[2] : g[4], k1 = top ? g[5] : g[7], k2 = top ? g[6] : g[8];
+      const float rw = 1.0f + ((g[0] + g[1] + g[3]) + 2.0f * (k0 + k1 + k2));
+      const float m = 0.5f * rw * U;
+      const float n1 = (k1 + sg * d13) - sg * m, n2 = (k2 - sg * d13) + sg * m;
+      g[4] = top ? k0 : g[4];
+      g[7] = top ? n1 : g[7];
+      g[8] = top ? n2 : g[8];
+      g[2] = top ? g[2] : k0;
+      g[5] = top ? g[5] : n1;
+      g[6] = top ? g[6] : n2;
       break;
     }
     case kWallMovingBB: {  // Eq. 11 with the node's own f* and density
       const float U = top ? p.u_top : p.u_bot;
       const float rho = 1.0f + (((fs[0] + fs[1]) + (fs[2] + fs[3])) + ((fs[4] + fs[5]) + (fs[6] + fs[7])) + fs[8]);
       const float m = rho * U * (1.0f / 6.0f);
-      if (top) {
-        g[4] = fs[2];
-        g[7] = fs[5] - m;
-        g[8] = fs[6] + m;
-      } else {
-        g[2] = fs[4];
-        g[5] = fs[7] + m;
-        g[6] = fs[8] - m;
-      }
+      const float k0 = top ? fs[2] : fs[4], k1 = top ? fs[5] : fs[7], k2 = top ? fs[6] : fs[8];
+      const float n1 = k1 - sg * m, n2 = k2 + sg * m;
+      g[4] = top ? k0 : g[4];
+      g[7] = top ? n1 : g[7];
+      g[8] = top ? n2 : g[8];
+      g[2] = top ? g[2] : k0;
+      g[5] = top ? g[5] : n1;
+      g[6] = top ? g[6] : n2;
       break;
     }
     default:
@@ -285,21 +287,28 @@ __device__ __forceinline__ void inlet_bc(const Physics& p, bool corner, float (&
 
 // Eq. 14: on each link the population f*_opp(k)(x) left along c_opp(k) and
 // g_k came back along c_k, giving the body (f*_opp(k) + g_k) c_opp(k); with
-// half-way bounce-back both are f*_opp(k): 2 c_opp(k) g_k.  `own` holds the
-// node's post-collision f* (read only with interpolated bounce-back).
-// Written to the node's fixed slot of this step's contributions.
+// half-way bounce-back both are f*_opp(k): 2 c_opp(k) g_k.  With full-way
+// bounce-back f*_opp(k)(x) enters the solid node now and comes back reversed
+// one step later; its whole exchange, 2 c_opp(k) f*_opp(k)(x), is booked
+// now.  `own` holds the node's post-collision f* (read by the interpolated
+// and full-way modes).  Written to the node's fixed slot of this step's
+// contributions.
 __device__ __forceinline__ void link_force(const Geometry& geo, double2* __restrict__ partial, int x, int y,
                                            uint16_t fl, const float (&g)[9], const float (&own)[9],
-                                           bool interp) {
+                                           const Physics& p) {
   double Fx = 0.0, Fy = 0.0;
 #pragma unroll
   for (int k = 1; k < 9; ++k)
     if ((fl >> k) & 1) {
       const double w = k < 5 ? 1.0 / 9.0 : 1.0 / 36.0;
-      if (interp) {
+      if (p.interp_bb) {
         const double sum = ((double)own[OPP[k]] + w) + ((double)g[k] + w);
         Fx -= (double)CX[k] * sum;
         Fy -= (double)CY[k] * sum;
+      } else if (p.full_bb) {
+        const double fo = (double)own[OPP[k]] + w;
+        Fx -= 2.0 * (double)CX[k] * fo;
+        Fy -= 2.0 * (double)CY[k] * fo;
       } else {
         const double fk = (double)g[k] + w;
         Fx -= 2.0 * (double)CX[k] * fk;
@@ -313,19 +322,19 @@ __device__ __forceinline__ void link_force(const Geometry& geo, double2* __restr
 // of a wall-row node (top row nodes 0 .. nx-3, bottom row nodes nx-2 ..
 // 2nx-5 of the closure's boundary numbering) and of an outlet node (nodes
 // 2(nx-2) ..).
+// (Selects rather than two branches: merged branches index g at run time,
+// which moves g to scratch memory.)
 __device__ __forceinline__ void closure_row(const StepArgs& a, int x, int y, float (&g)[9]) {
   if (!a.closure) return;
-  if (y == a.g.ny - 1) {
-    const float* r = a.closure + 3 * (x - 1);
-    g[4] += r[0];
-    g[7] += r[1];
-    g[8] += r[2];
-  } else {
-    const float* r = a.closure + 3 * ((a.g.nx - 2) + (x - 1));
-    g[2] += r[0];
-    g[6] += r[1];
-    g[5] += r[2];
-  }
+  const bool top = y == a.g.ny - 1;
+  const float* r = a.closure + 3 * ((top ? 0 : a.g.nx - 2) + (x - 1));
+  const float r0 = r[0], r1 = r[1], r2 = r[2];
+  g[4] = top ? g[4] + r0 : g[4];
+  g[7] = top ? g[7] + r1 : g[7];
+  g[8] = top ? g[8] + r2 : g[8];
+  g[2] = top ? g[2] : g[2] + r0;
+  g[6] = top ? g[6] : g[6] + r1;
+  g[5] = top ? g[5] : g[5] + r2;
 }
 
 __device__ __forceinline__ void closure_outlet(const StepArgs& a, int y, float (&g)[9]) {
@@ -357,7 +366,8 @@ __device__ __forceinline__ void gather(const StepArgs& a, int x, int y, uint16_t
 
 // Post-collision populations f*(t+1) of a node that is not plain bulk
 // fluid: pull, boundary corrections, force contributions (written when
-// `owner`), collision.  Solid nodes keep their (never streamed) values.
+// `owner`), collision.  Solid nodes keep their (never streamed) values, or
+// with full-way bounce-back pull theirs and send them back reversed.
 __device__ __forceinline__ void general_update(const StepArgs& a, int x, int y, bool owner, float (&out)[9],
                                                bool& bad) {
   const int nx = a.g.nx, ny = a.g.ny;
@@ -366,8 +376,15 @@ __device__ __forceinline__ void general_update(const StepArgs& a, int x, int y, 
   const bool corner_y = a.p.wall != kWallPeriodic && (y == 0 || y == ny - 1);
   const uint16_t fl = node_flags(a.g, x, y);
   if (fl & kSolid) {
+    if (a.p.full_bb) {
+      float g[9];
+      pull(a, x, y, 0, g);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) out[k] = load(a.A, a.g, k, x, y);
+      for (int k = 0; k < 9; ++k) out[k] = g[OPP[k]];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) out[k] = load(a.A, a.g, k, x, y);
+    }
     return;
   }
   float g[9];
@@ -391,11 +408,11 @@ __device__ __forceinline__ void general_update(const StepArgs& a, int x, int y, 
   if (open_x && x == 0) inlet_bc(a.p, corner_y, g);
   if ((fl >> 1) && owner) {
     float own[9];
-    if (a.p.interp_bb) {
+    if (a.p.interp_bb || a.p.full_bb) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) own[k] = load(a.A, a.g, k, x, y);
     }
-    link_force(a.g, a.partial, x, y, fl, g, own, a.p.interp_bb);
+    link_force(a.g, a.partial, x, y, fl, g, own, a.p);
   }
   collide(g, a.p, out, bad);
 }
@@ -688,7 +705,7 @@ __device__ __forceinline__ void second_update(const StepArgs& a, int x, int y, b
   float g[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    if (k > 0 && ((fl >> k) & 1)) {  // bounce-back on the cylinder
+    if (k > 0 && ((fl >> k) & 1) && !a.p.full_bb) {  // bounce-back on the cylinder
       if (interp) {
         const float q = a.g.q[8 * link_slot(a.g, x, y) + k - 1];
         g[k] = bfl(q, w1[OPP[k]], bh[k], w1[k]);
@@ -728,11 +745,11 @@ __device__ __forceinline__ void second_update(const StepArgs& a, int x, int y, b
   if (!active) return;
   if (fl & kSolid) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) out[k] = w1[k];
+    for (int k = 0; k < 9; ++k) out[k] = a.p.full_bb ? g[OPP[k]] : w1[k];
     return;
   }
   if (open_x && x == 0) inlet_bc(a.p, corner_y, g);
-  if ((fl >> 1) && owner) link_force(a.g, a.partial2, x, y, fl, g, w1, a.p.interp_bb);
+  if ((fl >> 1) && owner) link_force(a.g, a.partial2, x, y, fl, g, w1, a.p);
   collide(g, a.p, out, b);
   bad |= b && owner;
 }
@@ -754,10 +771,10 @@ __device__ __forceinline__ void load_pull(const StepArgs& a, int x, int y, float
 }
 
 // Interior waves, H = tile_y rows.  The row loop is unrolled; its loads run
-// two rows ahead, and the H output rows stay in registers until every load
-// of the wave has been issued, so no load waits behind a store (on this chip
-// one counter tracks both, and a wait for a load also waits for the older
-// stores).
+// two rows ahead (every load first for H <= 6), and the H output rows stay
+// in registers until every load of the wave has been issued, so no load
+// waits behind a store (on this chip one counter tracks both, and a wait for
+// a load also waits for the older stores).
 template <bool NT, int H>
 __device__ __forceinline__ void bulk_wave(const StepArgs& a, int strip, int seg) {
   const int lane = (int)(threadIdx.x & 63);
@@ -766,8 +783,6 @@ __device__ __forceinline__ void bulk_wave(const StepArgs& a, int strip, int seg)
   const int y0 = seg * H;
   const int x = xs - 1 + lane;
   const bool out_col = lane >= 1 && lane <= kStrip2;
-  // short segments issue every load of the wave first; longer ones keep
-  // two rows in flight
   constexpr int AHEAD = H <= 6 ? H + 2 : 2, R = AHEAD + 1;
   float w[3][9], pre[R][9], out[H][9];
 #pragma unroll
@@ -991,15 +1006,18 @@ __global__ void advance_kernel(int count, int64_t* dev_step, int* bad, int64_t* 
   *dev_step = base + count;
 }
 
-__global__ void init_eq_kernel(float* f, Geometry g, double u, double amp) {
+// Equilibrium of rho = 1 and the perturbed inlet velocity everywhere; with
+// `rest_solid` (full-way bounce-back) solid nodes start at rest, f = w.
+__global__ void init_eq_kernel(float* f, Geometry g, double u, double amp, int rest_solid) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= g.nx || y >= g.ny) return;
+  const bool rest = rest_solid && (node_flags(g, x, y) & kSolid);
   const double v = amp * u * sin(2.0 * 3.14159265358979323846 * y / (double)(g.ny - 1));
   const double usq = 1.5 * (u * u + v * v);
   for (int k = 0; k < 9; ++k) {
     const double w = k == 0 ? 4.0 / 9.0 : (k < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
     const double cu = CX[k] * u + CY[k] * v;
-    f[(int64_t)k * g.plane + (int64_t)y * g.pitch + x] = (float)(w * (cu * (3.0 + 4.5 * cu) - usq));
+    f[(int64_t)k * g.plane + (int64_t)y * g.pitch + x] = rest ? 0.0f : (float)(w * (cu * (3.0 + 4.5 * cu) - usq));
   }
 }
 
@@ -1158,8 +1176,10 @@ hipError_t launch_force_reduce(const double2* partials, int nnodes, int count, d
   return hipGetLastError();
 }
 
-hipError_t launch_init_equilibrium(float* f, const Geometry& g, double u, double amp, hipStream_t s) {
-  hipLaunchKernelGGL(init_eq_kernel, dim3((g.nx + 255) / 256, g.ny), dim3(256), 0, s, f, g, u, amp);
+hipError_t launch_init_equilibrium(float* f, const Geometry& g, double u, double amp, bool rest_solid,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(init_eq_kernel, dim3((g.nx + 255) / 256, g.ny), dim3(256), 0, s, f, g, u, amp,
+                     (int)rest_solid);
   return hipGetLastError();
 }
 

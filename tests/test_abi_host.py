@@ -62,7 +62,7 @@ def test_params_defaults_and_tau():
         dict(diameter=-1),
         dict(perturb_amp=math.inf),
         dict(collision=2),
-        dict(bounce=2),
+        dict(bounce=3),
         dict(collision=_lib.COLLISION_MRT, s_rates=(1, 2.0, 1.1, 1, 1.1, 1, 1.1, 0, 0)),
         dict(collision=_lib.COLLISION_MRT, s_rates=(1, 1.1, 1.1, 1, 0.0, 1, 1.1, 0, 0)),
         dict(collision=_lib.COLLISION_MRT, s_rates=(1, 1.1, 1.1, 1, 1.1, 1, 1.1, 2.5, 0)),

@@ -1,0 +1,144 @@
+"""GPU parity of the full-way bounce-back on the cylinder (Sec. 3.1) against
+the FP64 oracle, through the C ABI, and bit-for-bit agreement of every
+kernel variant and of the batched path.  Same bar as the half-way path:
+|d rho|, |d u|, |d f*| <= 1e-5 after the stated steps (here also on the
+solid nodes, which carry populations in this mode), forces to 1e-5 (lattice
+units) or Cd/Cl to 1e-3."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2605_02185_amd as lbm
+from lbm_inputs import PAPER_RATES, WORKLOADS, channel, perturbed_populations
+from parity_util import TOL, WT, _oracle_kwargs, compare_state, established, note, run_both
+
+pytestmark = pytest.mark.gpu
+
+FULL = dict(bounce=lbm.BOUNCE_FULLWAY)
+MRT = dict(collision=lbm.COLLISION_MRT, s_rates=PAPER_RATES)
+
+
+def _solid(kw):
+    return oracle.digitise(oracle.OracleParams(**_oracle_kwargs(kw)))
+
+
+def _solid_nodes_agree(lat, o, solid):
+    f = lat.get_populations(np.float64)
+    err = np.abs(f - o.get_fstar())[:, solid != 0].max()
+    note(f"  max |df*| on solid nodes {err:.2e}")
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("extra", [
+    dict(wall=lbm.WALL_FREE_SLIP),
+    dict(wall=lbm.WALL_MOVING_BB, outlet_mode=lbm.OUTLET_COPY_UNKNOWN),
+    dict(wall=lbm.WALL_PERIODIC, **MRT),
+    dict(wall=lbm.WALL_NEBB, tau=0.7, cx2=127, cy2=125),  # off-centre disk
+])
+def test_channel_random_state(extra):
+    kw = dict(channel(6, u=0.06), tau=0.6, **FULL)
+    kw.update(extra)
+    lat, o, (fx, fy, _, _), (ofx, ofy) = run_both(kw, 60, seed=400 + len(str(extra)))
+    solid = _solid(kw)
+    compare_state(lat, o, solid)
+    _solid_nodes_agree(lat, o, solid)
+    assert np.abs(fx - ofx).max() < 1e-5 and np.abs(fy - ofy).max() < 1e-5
+
+
+def test_initial_state_has_solid_at_rest():
+    kw = dict(channel(8, u=0.05), tau=0.6, **FULL)
+    lat = lbm.Lattice(lbm.make_params(**kw))
+    h = lat.get_populations(np.float64) - np.asarray(WT)[:, None, None]
+    solid = _solid(kw) != 0
+    assert np.abs(h[:, solid]).max() == 0.0
+
+
+def test_paper_lattice_fields_and_forces():
+    """800 x 400, D = 20, U = 0.02, Re = 100, MRT: 1500 steps from the initial
+    state, every node and the force trace against the oracle."""
+    kw = dict(WORKLOADS["cyl_d20_mrt"], **FULL)
+    lat, o, (fx, fy, cd, cl), (ofx, ofy) = run_both(kw, 1500)
+    solid = _solid(kw)
+    compare_state(lat, o, solid)
+    _solid_nodes_agree(lat, o, solid)
+    q = 0.5 * kw["u_in"] ** 2 * kw["diameter"]
+    dcd, dcl = np.abs(cd - ofx / q).max(), np.abs(cl - ofy / q).max()
+    note(f"  max |dCd| {dcd:.2e} max |dCl| {dcl:.2e}")
+    assert dcd < 1e-3 and dcl < 1e-3
+
+
+def test_full_size_two_steps_all_nodes():
+    """3280 x 1680 (D = 80, the two-step kernel by default) from a disturbed
+    state: every population of every node after two steps."""
+    kw = dict(WORKLOADS["cyl_d80"], **FULL)
+    lat, o, (fx, fy, _, _), (ofx, ofy) = run_both(kw, 2, seed=81, amp=0.02)
+    err = np.abs(lat.get_populations(np.float64) - o.get_fstar()).max()
+    note(f"  variant {lbm.variant_name(lat.variant)} max |df*| {err:.2e}")
+    assert err <= 1e-5
+    assert np.abs(fx - ofx).max() < 1e-5 and np.abs(fy - ofy).max() < 1e-5
+
+
+@pytest.mark.parametrize("kw", [dict(channel(10, u=0.05), tau=0.6, **FULL),
+                                dict(WORKLOADS["cyl_d20_mrt"], **FULL)])
+def test_variants_are_bitwise_identical(kw):
+    ref = None
+    for v in range(1, lbm.num_variants() + 1):
+        lat = lbm.Lattice(lbm.make_params(**kw))
+        lat.set_variant(v)
+        lat.set_populations(perturbed_populations(4, kw["ny"], kw["nx"], WT, 0.03, dtype=np.float32))
+        lat.step(131)
+        f, forces = lat.get_populations(), lat.forces()
+        lat.close()
+        if ref is None:
+            ref = (f, forces)
+            continue
+        note(f"  variant {lbm.variant_name(v)}")
+        assert np.array_equal(f, ref[0]), v
+        for a, b in zip(forces, ref[1]):
+            if a is not None:
+                assert np.array_equal(a, b), v
+
+
+def test_ensemble_matches_separate_runs_bitwise():
+    cases = [dict(channel(6, u=0.05), tau=0.62, **FULL),
+             dict(channel(9, u=0.05), tau=0.58, wall=lbm.WALL_PERIODIC, **FULL, **MRT),
+             dict(channel(7, u=0.05), tau=0.6)]
+    note(f"full-way ensemble of {len(cases)} cases")
+    ens = lbm.Ensemble([lbm.make_params(**kw) for kw in cases])
+    ens.step(211)
+    ens.sync()
+    for i, kw in enumerate(cases):
+        lat = lbm.Lattice(lbm.make_params(**kw))
+        lat.step(211)
+        assert np.array_equal(ens.get_populations(i, np.float64), lat.get_populations(np.float64)), i
+        for a, c in zip(ens.forces(i), lat.forces()):
+            if a is not None:
+                assert np.array_equal(a, c), i
+        lat.close()
+
+
+def _shedding(kw, steps=300000, window=50000):
+    lat = lbm.Lattice(lbm.make_params(**kw, hist_capacity=window + 16))
+    lat.step(steps)
+    assert lat.diverged_step() == 0
+    _, _, cd, cl = lat.forces(steps - window + 1, window)
+    lat.close()
+    s = lbm.shedding_stats(cd, cl, kw["diameter"], kw["u_in"], 6)
+    ok, amps = established(cl, n=3)
+    note(f"  bounce {kw.get('bounce', 0)}: {s}, per-period lift amplitudes {np.round(amps, 4)}")
+    assert ok
+    return s
+
+
+@pytest.mark.timeout(300)
+def test_e1_shedding_close_to_half_way():
+    """The paper's E1 run (800 x 400, D = 20, MRT) with full-way bounce-back:
+    the wall sits where half-way puts it and only the return is one step
+    later, so the shedding statistics stay within 1 % (mean Cd, St) and 3 %
+    (lift amplitude) of the half-way run, inside Table 2's band."""
+    full = _shedding(dict(WORKLOADS["cyl_d20_mrt"], **FULL))
+    half = _shedding(dict(WORKLOADS["cyl_d20_mrt"]))
+    assert 1.3 <= full["mean_cd"] <= 1.6 and 0.28 <= full["cl_amp"] <= 0.45 and 0.155 <= full["st"] <= 0.175
+    assert abs(full["mean_cd"] / half["mean_cd"] - 1) < 0.01
+    assert abs(full["st"] / half["st"] - 1) < 0.01
+    assert abs(full["cl_amp"] / half["cl_amp"] - 1) < 0.03
