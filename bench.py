@@ -192,9 +192,10 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": args.workload,
-            "nx": w["nx"], "ny": w["ny"], "diameter": w["diameter"], "u_in": w["u_in"],
-            "re": w["re"], "tau": round(lbm.tau_of(p), 6), "wall": "free-slip",
-            "outlet": "copy-all", "collision": args.collision, "variant": vname,
+            "nx": w["nx"], "ny": w["ny"], "diameter": w.get("diameter", 0), "u_in": w["u_in"],
+            "re": w.get("re"), "tau": round(lbm.tau_of(p), 6), "wall": "free-slip",
+            "outlet": "x-periodic" if w.get("x_periodic") else "copy-all", "collision": args.collision,
+            "variant": vname,
             "graphs": not args.no_graphs,
         },
         "roofline": roof,

@@ -58,6 +58,10 @@ WORKLOADS = {
     "cyl_d160": channel(160),
     "cyl_d20_mrt": paper_channel(20),
     "cyl_d40_mrt": paper_channel(40),
+    # one GPU's share of the D = 160 channel cut into eight slabs along x:
+    # 820 of its 6560 columns, no cylinder; the x-periodic wrap stands in for
+    # the ghost columns the neighbouring slabs would fill
+    "slab_d160_of8": dict(nx=820, ny=3360, diameter=0, u_in=0.05, re=100.0, tau=0.74, x_periodic=True),
 }
 
 

@@ -843,13 +843,11 @@ __device__ __forceinline__ void general_wave(const StepArgs& a, int segment, int
   prefetch_bulk(a, x, row_of(y0 - 1), pre);
   prefetch_bulk(a, x, row_of(y0), pre1);
   bool bad1 = false, bad2 = false;
-  // unrolled, with the output rows held until the last load has been issued
-  // (a wait for a load also waits for every older store)
-  float outb[kSub2][9];
-#pragma unroll
-  for (int i = 0; i < kSub2 + 2; ++i) {
-    const int r = y0 - 1 + i;
-    if (r > y1) break;  // short sub-segment at the lattice's last rows
+  // A rolled loop: unrolled copies of the boundary code (several times the
+  // bulk path's size) crowd the instruction cache the bulk waves on the same
+  // CU run from, which costs the whole launch more than these waves gain.
+#pragma unroll 1
+  for (int r = y0 - 1; r <= y1; ++r) {
     float nxt[9];
     prefetch_bulk(a, x, row_of(r + 2), nxt);
 #pragma unroll
@@ -865,12 +863,13 @@ __device__ __forceinline__ void general_wave(const StepArgs& a, int segment, int
       pre[k] = pre1[k];
       pre1[k] = nxt[k];
     }
-    if (i >= 2) second_update(a, x, r - 1, col_ok, out_col, w0, w1, w2, outb[i - 2], bad2);
+    if (r > y0) {
+      const int y2 = r - 1;
+      float out[9];
+      second_update(a, x, y2, col_ok, out_col, w0, w1, w2, out, bad2);
+      if (out_col) store9<NT>(a.B, P, (uint32_t)y2 * Wp + (uint32_t)x, out);
+    }
   }
-  if (out_col)
-#pragma unroll
-    for (int j = 0; j < kSub2; ++j)
-      if (y0 + j < y1) store9<NT>(a.B, P, (uint32_t)(y0 + j) * Wp + (uint32_t)x, outb[j]);
   report_bad(a.bad, bad1, a.slot);
   report_bad(a.bad, bad2, a.slot + 1);
 }

@@ -82,7 +82,7 @@ def test_c1_force_trace_2000_steps():
     assert dcd < 1e-3 and dcl < 1e-3
 
 
-@pytest.mark.parametrize("name", ["cyl_d80", "cyl_d160"])
+@pytest.mark.parametrize("name", ["cyl_d80", "cyl_d160", "slab_d160_of8"])
 def test_full_size_two_steps_all_nodes(name):
     """The benchmark's lattices in the benchmark's launch configuration:
     two steps from a disturbed state, every node against the oracle."""
