@@ -195,9 +195,10 @@ lbm_status lbm_shedding_stats(const double* cd, const double* cl, int64_t n, dou
  * registers, so one launch reads and writes each population once for two
  * node updates; single steps (an odd remainder, or the steps of a learned
  * closure evaluated every step) then run the one-step kernel.  The default of
- * a new context is the two-step "t2_h4" for lattices of 2^20 nodes or more
- * and the one-step "v1_ty1_xcd" (cached stores, each XCD on its own band of
- * rows) below.  lbm_get_variant reports the variant in use. */
+ * a new context is the two-step "t2_h4_s4" (boundary segments run in 4-row
+ * pieces) from 2^21 nodes, "t2_h4" (2-row pieces) from 2^20, and the
+ * one-step "v1_ty1_xcd" (cached stores, each XCD on its own band of rows)
+ * below.  lbm_get_variant reports the variant in use. */
 int32_t lbm_num_variants(void);
 lbm_status lbm_set_variant(lbm_ctx* ctx, int32_t variant);
 int32_t lbm_get_variant(const lbm_ctx* ctx);

@@ -69,7 +69,6 @@ struct Tiling {
 // hold one more column on either side) of one segment of tile_y rows.
 // Without x-periodicity the strips are aligned to the right edge.
 constexpr int kStrip2 = 62;
-constexpr int kSub2 = 2;  // rows per wave where a segment needs boundary code
 
 __host__ __device__ inline int strip_start(const Geometry& g, const Tiling& t, bool x_periodic, int strip) {
   return x_periodic ? strip * kStrip2 : g.nx - kStrip2 * (t.ntx - strip);
@@ -124,6 +123,7 @@ struct Variant {
   int vx;              // consecutive nodes per lane on the bulk path
   int remap_xcd, nontemporal;
   int steps;           // time steps per launch (1, or 2 with the intermediate state in registers)
+  int sub;             // two-step: rows per wave of the segments that need the boundary code
 };
 
 // Kernel launchers (lbm_kernels.hip).  All return the launch status.

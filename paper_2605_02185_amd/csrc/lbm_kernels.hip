@@ -819,8 +819,9 @@ __device__ __forceinline__ void bulk_wave(const StepArgs& a, int strip, int seg)
   for (int j = 0; j < H; ++j) store9<NT>(a.B, P, (uint32_t)(y0 + j) * Wp + (uint32_t)x, out[j]);
 }
 
-// kSub2 rows of a segment that is not interior, with the boundary code.
-template <bool NT>
+// SUB rows (fewer at the segment's or the lattice's end) of a segment that
+// is not interior, with the boundary code.
+template <bool NT, int SUB>
 __device__ __forceinline__ void general_wave(const StepArgs& a, int segment, int sub) {
   const int lane = (int)(threadIdx.x & 63);
   const int S = a.t.ntx, H = a.t.tile_y;
@@ -828,9 +829,9 @@ __device__ __forceinline__ void general_wave(const StepArgs& a, int segment, int
   const int nx = a.g.nx, ny = a.g.ny;
   const bool xper = a.p.x_periodic, yper = a.p.wall == kWallPeriodic;
   const int xs = strip_start(a.g, a.t, xper, strip);
-  const int y0 = seg * H + sub * kSub2;
+  const int y0 = seg * H + sub * SUB;
   if (y0 >= ny) return;
-  const int y1 = min(y0 + kSub2, ny);
+  const int y1 = min(min(y0 + SUB, seg * H + H), ny);
   const int ux = xs - 1 + lane;  // column before wrapping
   const int x = xper ? ((ux % nx) + nx) % nx : ux;
   const bool col_ok = xper || (ux >= 0 && ux < nx);
@@ -875,21 +876,23 @@ __device__ __forceinline__ void general_wave(const StepArgs& a, int segment, int
 }
 
 // One launch, two steps.  The first blocks take the boundary sub-segments
-// (listed on the host, kSub2 rows each, so that they are many and short and
-// run alongside the interior ones); the later ones one segment per wave, in
+// (segments listed on the host, cut into SUB rows each so that they run
+// alongside the interior ones: 2 rows keep them short where the launch is
+// short, 4 halve their recomputed rows where it is long); the later blocks
+// one segment per wave, in
 // row-major order of (segment, strip), so that the waves in flight at any
 // time cover a narrow band of rows, four neighbouring strips per block.
 // (Orders that keep vertically adjacent segments on one XCD, so that their
 // shared rows are read once into its L2, fetch 30 % fewer bytes but ran
 // 4-10 % slower: the plain order's DRAM locality wins.)
-template <bool NT, int H>
+template <bool NT, int H, int SUB>
 __global__ __launch_bounds__(256) void step2_kernel(StepArgs a) {
-  constexpr int per = H / kSub2;
+  constexpr int per = (H + SUB - 1) / SUB;
   const int gen_blocks = (a.n_gen * per + 3) / 4;
   const int b = (int)blockIdx.x, w = (int)(threadIdx.x >> 6);
   if (b < gen_blocks) {
     const int wave = b * 4 + w;
-    if (wave < a.n_gen * per) general_wave<NT>(a, a.gen[wave / per], wave % per);
+    if (wave < a.n_gen * per) general_wave<NT, SUB>(a, a.gen[wave / per], wave % per);
     return;
   }
   const int wave = (b - gen_blocks) * 4 + w;
@@ -1070,22 +1073,24 @@ __global__ __launch_bounds__(256) void copy_probe_kernel(const float4v* __restri
 }
 
 constexpr Variant kVariants[] = {
-    // name              tile_x tile_y vx remap nt steps
-    {"v1_ty1_nt", 256, 1, 1, 0, 1, 1},
-    {"v1_ty1_xcd_nt", 256, 1, 1, 1, 1, 1},
-    {"v1_ty1", 256, 1, 1, 0, 0, 1},
-    {"v1_ty2_nt", 256, 2, 1, 0, 1, 1},
-    {"v2_ty1_nt", 512, 1, 2, 0, 1, 1},
-    {"v4_ty1_nt", 1024, 1, 4, 0, 1, 1},
-    {"v4_ty1_xcd_nt", 1024, 1, 4, 1, 1, 1},
-    {"v1_ty1_xrow_nt", 256, 1, 1, 2, 1, 1},
-    {"v2_ty1_xrow_nt", 512, 1, 2, 2, 1, 1},
-    {"v1_ty1_xcd", 256, 1, 1, 1, 0, 1},
-    {"t2_h4", kStrip2, 4, 1, 0, 0, 2},
-    {"t2_h6", kStrip2, 6, 1, 0, 0, 2},
-    {"t2_h8", kStrip2, 8, 1, 0, 0, 2},
-    {"t2_h8_nt", kStrip2, 8, 1, 0, 1, 2},
-    {"t2_h16", kStrip2, 16, 1, 0, 0, 2},
+    // name              tile_x tile_y vx remap nt steps sub
+    {"v1_ty1_nt", 256, 1, 1, 0, 1, 1, 0},
+    {"v1_ty1_xcd_nt", 256, 1, 1, 1, 1, 1, 0},
+    {"v1_ty1", 256, 1, 1, 0, 0, 1, 0},
+    {"v1_ty2_nt", 256, 2, 1, 0, 1, 1, 0},
+    {"v2_ty1_nt", 512, 1, 2, 0, 1, 1, 0},
+    {"v4_ty1_nt", 1024, 1, 4, 0, 1, 1, 0},
+    {"v4_ty1_xcd_nt", 1024, 1, 4, 1, 1, 1, 0},
+    {"v1_ty1_xrow_nt", 256, 1, 1, 2, 1, 1, 0},
+    {"v2_ty1_xrow_nt", 512, 1, 2, 2, 1, 1, 0},
+    {"v1_ty1_xcd", 256, 1, 1, 1, 0, 1, 0},
+    {"t2_h4", kStrip2, 4, 1, 0, 0, 2, 2},
+    {"t2_h6", kStrip2, 6, 1, 0, 0, 2, 2},
+    {"t2_h8", kStrip2, 8, 1, 0, 0, 2, 2},
+    {"t2_h8_nt", kStrip2, 8, 1, 0, 1, 2, 2},
+    {"t2_h16", kStrip2, 16, 1, 0, 0, 2, 2},
+    {"t2_h4_s4", kStrip2, 4, 1, 0, 0, 2, 4},
+    {"t2_h6_s4", kStrip2, 6, 1, 0, 0, 2, 4},
 };
 
 }  // namespace
@@ -1097,9 +1102,13 @@ const Variant& variant(int v) { return kVariants[v - 1]; }
 // 5.5 M nodes, even at 1.4 M, slower below).  Smaller lattices live in the
 // caches: there the one-step kernel with cached stores and each XCD on its
 // own band of rows is fastest (10-25 % over the plain order at 86 k-800 k
-// nodes; the plain order wins once the lattice streams from HBM).
+// nodes; the plain order wins once the lattice streams from HBM).  Boundary
+// waves of 4 rows gain 2-17 % from 2.8 M nodes on and lose 25 % at 1.4 M,
+// where the launch lasts about as long as one such wave.
 int default_variant(int64_t nodes) {
-  const char* want = nodes >= ((int64_t)1 << 20) ? "t2_h4" : "v1_ty1_xcd";
+  const char* want = nodes >= ((int64_t)1 << 21) ? "t2_h4_s4"
+                     : nodes >= ((int64_t)1 << 20) ? "t2_h4"
+                                                   : "v1_ty1_xcd";
   for (int v = 1; v <= num_variants(); ++v)
     if (std::strcmp(kVariants[v - 1].name, want) == 0) return v;
   return 1;
@@ -1136,18 +1145,21 @@ hipError_t launch_force_reduce_batch(const CaseArgs* cases, int ncases, int coun
 hipError_t launch_step(const StepArgs& a, int v, hipStream_t s) {
   const Variant& var = variant(v);
   if (var.steps == 2) {
-    const int blocks = (a.n_gen * (var.tile_y / kSub2) + 3) / 4 + (a.t.ntx * a.t.nty + 3) / 4;
+    const int per = (var.tile_y + var.sub - 1) / var.sub;
+    const int blocks = (a.n_gen * per + 3) / 4 + (a.t.ntx * a.t.nty + 3) / 4;
     const dim3 grid((unsigned)blocks), block(256);
-#define LBM_T2(NT, H)                                                      \
-  if (var.nontemporal == NT && var.tile_y == H) {                          \
-    hipLaunchKernelGGL((step2_kernel<NT, H>), grid, block, 0, s, a);       \
+#define LBM_T2(NT, H, SUB)                                                 \
+  if (var.nontemporal == NT && var.tile_y == H && var.sub == SUB) {        \
+    hipLaunchKernelGGL((step2_kernel<NT, H, SUB>), grid, block, 0, s, a);  \
     return hipGetLastError();                                              \
   }
-    LBM_T2(false, 4)
-    LBM_T2(false, 6)
-    LBM_T2(false, 8)
-    LBM_T2(true, 8)
-    LBM_T2(false, 16)
+    LBM_T2(false, 4, 2)
+    LBM_T2(false, 6, 2)
+    LBM_T2(false, 8, 2)
+    LBM_T2(true, 8, 2)
+    LBM_T2(false, 16, 2)
+    LBM_T2(false, 4, 4)
+    LBM_T2(false, 6, 4)
 #undef LBM_T2
     return hipErrorInvalidValue;
   }

@@ -260,12 +260,16 @@ def test_two_step_variants_match_one_step_bitwise(case):
 
 
 def test_default_variant_follows_the_lattice_size():
-    """Two steps per launch from 2^20 nodes on, one below (cached stores, XCD
-    bands); variant 0 restores the default."""
+    """Two steps per launch from 2^20 nodes on (boundary waves of 4 rows from
+    2^21), one below (cached stores, XCD bands); variant 0 restores the
+    default."""
     small = lbm.Lattice(lbm.make_params(**WORKLOADS["cyl_d10"]))
     big = lbm.Lattice(lbm.make_params(**WORKLOADS["cyl_d40"]))
     assert lbm.variant_name(small.variant) == "v1_ty1_xcd"
     assert lbm.variant_name(big.variant) == "t2_h4"
+    bigger = lbm.Lattice(lbm.make_params(**WORKLOADS["slab_d160_of8"]))
+    assert lbm.variant_name(bigger.variant) == "t2_h4_s4"
+    bigger.close()
     big.set_variant(1)
     assert big.variant == 1
     big.set_variant(0)
