@@ -36,8 +36,8 @@ def main():
     ap.add_argument("--collision", default="bgk")
     ap.add_argument("--variant", required=True)
     a = ap.parse_args()
-    two = a.variant.startswith("t2_")
-    kname = "step2_kernel" if two else "step_kernel<"
+    steps = {"t2": 2, "t3": 3}.get(a.variant[:2], 1)
+    kname = {2: "step2_kernel", 3: "step3_kernel"}.get(steps, "step_kernel<")
     w = WORKLOADS[a.workload]
     nodes = w["nx"] * w["ny"]
     copy_bytes = 9 * nodes * 4
@@ -50,7 +50,6 @@ def main():
     write_scale = w_copy * 1024 / copy_bytes
     read_b = f_step * 1024 / fetch_scale
     write_b = w_step * 1024 / write_scale
-    steps = 2 if two else 1
     alg = bench.BYTES_PER_NODE * nodes * steps
     state = bench.BYTES_PER_NODE * nodes
     out = {

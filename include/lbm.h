@@ -190,22 +190,24 @@ lbm_status lbm_shedding_stats(const double* cd, const double* cl, int64_t n, dou
 
 /* Kernel selection for measurement and autotuning.  Valid variants are
  * 1..lbm_num_variants(); variant 0 selects the context's default.  The result
- * is bit-identical for every variant.  Variants named "t2_*" advance two time
- * steps per launch and keep the intermediate populations f*(t+1) in
+ * is bit-identical for every variant.  Variants named "t2_*" ("t3_*") advance
+ * two (three) time steps per launch and keep the intermediate populations in
  * registers, so one launch reads and writes each population once for two
- * node updates; single steps (an odd remainder, or the steps of a learned
- * closure evaluated every step) then run the one-step kernel.  The default of
- * a new context is the two-step "t2_h4_s4" (boundary segments run in 4-row
- * pieces) from 2^21 nodes, "t2_h4" (2-row pieces) from 2^20, and the
- * one-step "v1_ty1_xcd" (cached stores, each XCD on its own band of rows)
- * below.  lbm_get_variant reports the variant in use. */
+ * (three) node updates; the steps left over (a remainder of n, or the steps
+ * of a learned closure, which "t3_*" variants run one at a time) run the
+ * one-step kernel.  The default of
+ * a new context is "t3_h8_s8" from 2^24 nodes, "t3_h8_s4" from 2^22,
+ * "t3_h8_s8" from 2^21, "t2_h4" from 2^20 and the one-step "v1_ty1_xcd"
+ * (cached stores, each XCD on its own band of rows) below ("_sN": segments
+ * that need the boundary code run in pieces of N rows).  lbm_get_variant
+ * reports the variant in use. */
 int32_t lbm_num_variants(void);
 lbm_status lbm_set_variant(lbm_ctx* ctx, int32_t variant);
 int32_t lbm_get_variant(const lbm_ctx* ctx);
 const char* lbm_variant_name(int32_t variant);
 
 /* Step scheduling.  With graphs enabled (the default) lbm_step replays HIP
- * graphs that each hold 64 steps plus the force-history reduction, captured
+ * graphs that each hold 96 steps plus the force-history reduction, captured
  * once per context on an internal stream and launched on the context's
  * stream; the remainder of n runs as plain launches.  Results are identical
  * bit for bit either way. */
@@ -227,7 +229,7 @@ lbm_status lbm_autotune(lbm_ctx* ctx, int32_t steps, const char* cache_path, int
 /* ------------------------------------------------------------------ ensemble
  * An ensemble advances many independent lattices (e.g. cylinder channels of
  * different D, Re and size) together: every step is one kernel launch over a
- * flattened list of the tiles of all active cases, and 64-step chunks are
+ * flattened list of the tiles of all active cases, and 96-step chunks are
  * replayed as HIP graphs.  Each case evolves bit for bit as it would in its
  * own context.  Cases are identified by their index in the `cases` array. */
 typedef struct lbm_batch lbm_batch;
@@ -354,8 +356,9 @@ lbm_status lbm_closure_disable(lbm_ctx* ctx);
  * the inlet or the outlet column keep the plain treatment (default 0). */
 lbm_status lbm_closure_set_filter(lbm_ctx* ctx, float beta, int32_t taper);
 
-/* Evaluate the network only every `interval` steps (1, 2, 4, 8, 16, 32 or
- * 64; default 1) and apply the held residual in between, at the steps whose
+/* Evaluate the network only every `interval` steps (a divisor of 96: 1, 2,
+ * 3, 4, 6, 8, 12, 16, 24, 32, 48 or 96; default 1) and apply the held
+ * residual in between, at the steps whose
  * index since lbm_create is a multiple of `interval`.  With an even interval
  * the context keeps its two-step launches (pairs that start on an evaluation
  * step), the held residual entering both steps of a pair; the results are

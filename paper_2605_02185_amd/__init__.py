@@ -164,7 +164,7 @@ class Lattice:
         check(_lib.lib.lbm_closure_set_filter(self._h, beta, taper))
 
     def set_closure_interval(self, interval: int = 1):
-        """Evaluate the network every `interval` steps (a divisor of 64)."""
+        """Evaluate the network every `interval` steps (a divisor of 96)."""
         check(_lib.lib.lbm_closure_set_interval(self._h, interval))
 
     def disable_closure(self):

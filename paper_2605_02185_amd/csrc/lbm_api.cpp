@@ -198,6 +198,7 @@ struct lbm_ctx {
   int use_graphs = 1;
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+  int graph_flip[2] = {0, 0};  // 1: graph[c] leaves the state in buf[c ^ 1] (an odd number of launches)
   // learned closure
   const lbm_mlp* mlp = nullptr;
   int closure_mask = 7;
@@ -319,7 +320,7 @@ namespace {
 lbm_status set_tiling(lbm_ctx* c, int v) {
   lbm::Tiling t;
   lbm::tiling_for_variant(c->geo, v, &t);
-  if (lbm::variant(v).steps == 2) {
+  if (lbm::variant(v).steps >= 2) {
     std::vector<int> gen;
     for (int seg = 0; seg < t.nty; ++seg)
       for (int strip = 0; strip < t.ntx; ++strip)
@@ -502,10 +503,19 @@ bool pairable(const lbm_ctx* c) {
   return !c->mlp || (c->closure_interval % 2 == 0 && (c->step + 1) % c->closure_interval != 0);
 }
 
-// Enqueues k = 1 or 2 steps (k = 2 only when pairable) on stream s, buffers by
-// c->cur and ring slots from c->pending, and advances the host-side
-// bookkeeping; folds the ring when it is full.  One launch always moves the
-// state from buf[cur] to buf[cur ^ 1].
+// Steps of the next launch, with `left` steps still to go: the variant's two
+// or three when they fit (three only without a learned closure), else one.
+int group(const lbm_ctx* c, int64_t left) {
+  const int s = lbm::variant(c->variant).steps;
+  if (s == 3 && left >= 3 && !c->mlp && c->pending + 3 <= lbm::kRing) return 3;
+  if (s == 2 && left >= 2 && pairable(c)) return 2;
+  return 1;
+}
+
+// Enqueues k = 1, 2 or 3 steps (k > 1 only as group() allows) on stream s,
+// buffers by c->cur and ring slots from c->pending, and advances the
+// host-side bookkeeping; folds the ring when it is full.  One launch always
+// moves the state from buf[cur] to buf[cur ^ 1].
 lbm_status enqueue_step(lbm_ctx* c, hipStream_t s, int k = 1) {
   lbm::StepArgs a{};
   a.g = c->geo;
@@ -517,12 +527,13 @@ lbm_status enqueue_step(lbm_ctx* c, hipStream_t s, int k = 1) {
   a.slot = c->pending;
   a.partial = c->d_partials + (size_t)c->pending * slots_of(c);
   int v = c->variant;
-  if (k == 2) {
+  if (k >= 2) {
     a.partial2 = a.partial + slots_of(c);
+    a.partial3 = k == 3 ? a.partial2 + slots_of(c) : nullptr;
     a.gen = c->d_gen;
     a.n_gen = c->n_gen;
   } else if (lbm::variant(v).steps != 1) {
-    v = 1;  // a single step of a two-step variant: the plain one-step kernel
+    v = 1;  // a single step of a multi-step variant: the plain one-step kernel
     lbm::tiling_for_variant(c->geo, v, &a.t);
   }
   if (c->mlp) {
@@ -552,8 +563,9 @@ lbm_status capture(lbm_ctx* c) {
   const int64_t step0 = c->step;
   HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
   lbm_status st = LBM_OK;
-  for (int i = 0; i < lbm::kRing && st == LBM_OK;) {
-    const int k = pairable(c) ? 2 : 1;
+  int launches = 0;
+  for (int i = 0; i < lbm::kRing && st == LBM_OK; ++launches) {
+    const int k = group(c, lbm::kRing - i);
     st = enqueue_step(c, c->capture_stream, k);
     i += k;
   }
@@ -570,6 +582,7 @@ lbm_status capture(lbm_ctx* c) {
   const hipError_t e2 = hipGraphInstantiate(&c->graph[cur0], g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e2 != hipSuccess) return fail(LBM_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+  c->graph_flip[cur0] = launches & 1;
   return LBM_OK;
 }
 
@@ -729,7 +742,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   // step index is a multiple of its interval, so that every graph replays
   // the evaluations at the same places), then whole graphs
   while (i < n && (c->pending != 0 || (c->mlp && c->step % c->closure_interval != 0))) {
-    const int k = n - i >= 2 && pairable(c) ? 2 : 1;
+    const int k = group(c, n - i);
     lbm_status st = enqueue_step(c, c->stream, k);
     if (st != LBM_OK) return st;
     i += k;
@@ -741,14 +754,13 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
         if (st != LBM_OK) return st;
       }
       HIP_TRY(hipGraphLaunch(c->graph[c->cur], c->stream));
-      // kRing steps take an even number of launches (kRing one-step ones or
-      // kRing/2 two-step ones): the state returns to the same buffer
+      c->cur ^= c->graph_flip[c->cur];
       c->step += lbm::kRing;
       i += lbm::kRing;
     }
   }
   while (i < n) {
-    const int k = n - i >= 2 && pairable(c) ? 2 : 1;
+    const int k = group(c, n - i);
     lbm_status st = enqueue_step(c, c->stream, k);
     if (st != LBM_OK) return st;
     i += k;

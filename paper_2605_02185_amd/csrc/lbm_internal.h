@@ -18,7 +18,7 @@ enum : int { kOutletCopyAll = 0, kOutletCopyUnknown = 1 };
 // Force partials of one step live in a ring of kRing steps; a reduction
 // kernel folds them into the FP64 history every kRing steps (and at the end
 // of every lbm_step call).
-constexpr int kRing = 64;
+constexpr int kRing = 96;
 
 // Node flags inside the cylinder rectangle: bit 0 = solid node; bit k
 // (k = 1..8) = the pull source x - c_k of this fluid node is solid, so
@@ -65,23 +65,29 @@ struct Tiling {
   int remap_xcd;         // block-to-tile map: 0 plain, 1 XCD bands, 2 XCD-interleaved rows
 };
 
-// Two steps per launch: each wave owns kStrip2 output columns (its 64 lanes
-// hold one more column on either side) of one segment of tile_y rows.
-// Without x-periodicity the strips are aligned to the right edge.
+// Two or three steps per launch: each wave owns tile_x output columns (its
+// 64 lanes hold one more column on either side per step beyond the first:
+// kStrip2 = 62 for two steps, kStrip3 = 60 for three) of one segment of
+// tile_y rows.  Without x-periodicity the strips are aligned to the right
+// edge.
 constexpr int kStrip2 = 62;
+constexpr int kStrip3 = 60;
+
+__host__ __device__ inline int strip_halo(const Tiling& t) { return (64 - t.tile_x) / 2; }
 
 __host__ __device__ inline int strip_start(const Geometry& g, const Tiling& t, bool x_periodic, int strip) {
-  return x_periodic ? strip * kStrip2 : g.nx - kStrip2 * (t.ntx - strip);
+  return x_periodic ? strip * t.tile_x : g.nx - t.tile_x * (t.ntx - strip);
 }
 
 // A segment is interior when it has the full tile_y rows and every node its
-// wave updates in the first step (columns xs-1 .. xs+62, rows y0-1 .. y0+H)
-// is plain bulk fluid: away from the edges and outside the cylinder's flag
-// rectangle.  The others need the boundary code.
+// wave updates in the first step (h = strip_halo columns and rows beyond the
+// segment on every side) is plain bulk fluid: away from the edges and outside
+// the cylinder's flag rectangle.  The others need the boundary code.
 __host__ __device__ inline bool interior_segment(const Geometry& g, const Tiling& t, bool x_periodic, int strip,
                                                  int seg) {
+  const int h = strip_halo(t);
   const int xs = strip_start(g, t, x_periodic, strip), y0 = seg * t.tile_y;
-  const int xa = xs - 1, xb = xs + kStrip2, ya = y0 - 1, yb = y0 + t.tile_y;
+  const int xa = xs - h, xb = xs + t.tile_x - 1 + h, ya = y0 - h, yb = y0 + t.tile_y - 1 + h;
   if (xa < 1 || xb > g.nx - 2 || ya < 1 || yb > g.ny - 2) return false;
   return !(xa < g.rx0 + g.rw && xb >= g.rx0 && ya < g.ry0 + g.rh && yb >= g.ry0);
 }
@@ -93,8 +99,9 @@ struct StepArgs {
   Physics p;
   Tiling t;
   double2* partial;             // this step's force contributions [n_link_nodes]
-  double2* partial2;            // the second step's, for kernels that take two steps
-  const int* gen;               // two-step launches: segments (seg * ntx + strip) that are not interior
+  double2* partial2;            // the second step's, for kernels that take two or three steps
+  double2* partial3;            // the third step's, for kernels that take three
+  const int* gen;               // multi-step launches: segments (seg * ntx + strip) that are not interior
   int n_gen;
   const float* closure;         // learned-closure residuals [boundary node][3], or null
   int* bad;                     // watchdog: min ring slot with a bad density
@@ -122,7 +129,7 @@ struct Variant {
                        // variants the output columns per wave and rows per segment
   int vx;              // consecutive nodes per lane on the bulk path
   int remap_xcd, nontemporal;
-  int steps;           // time steps per launch (1, or 2 with the intermediate state in registers)
+  int steps;           // time steps per launch (1, or 2-3 with the intermediate states in registers)
   int sub;             // two-step: rows per wave of the segments that need the boundary code
 };
 

@@ -659,11 +659,14 @@ __device__ __forceinline__ void first_update(const StepArgs& a, int x, int y, bo
 }
 
 // f*(t+2) at (x, y) from f*(t+1) of rows y-1 (w0), y (w1) and y+1 (w2) of
-// this lane's column and its two neighbour lanes.  The same steps as
-// general_update, with the pulled values taken from registers.
-__device__ __forceinline__ void second_update(const StepArgs& a, int x, int y, bool active, bool owner,
-                                              const float (&w0)[9], const float (&w1)[9], const float (&w2)[9],
-                                              float (&out)[9], bool& bad) {
+// this lane's column and its two neighbour lanes (or one level up: f*(t+3)
+// from f*(t+2)).  The same steps as general_update, with the pulled values
+// taken from registers; link forces go to `partial`.  Inactive lanes leave
+// `out` unset (nothing reads it: their node is outside the lattice).
+__device__ __forceinline__ void second_update(const StepArgs& a, double2* __restrict__ partial, int x, int y,
+                                              bool active, bool owner, const float (&w0)[9],
+                                              const float (&w1)[9], const float (&w2)[9], float (&out)[9],
+                                              bool& bad) {
   const int nx = a.g.nx, ny = a.g.ny;
   // f*_k(x - c_k, y - c_k,y): row by c_y, the lane to the left for c_x = +1
   float c[9];
@@ -749,7 +752,7 @@ __device__ __forceinline__ void second_update(const StepArgs& a, int x, int y, b
     return;
   }
   if (open_x && x == 0) inlet_bc(a.p, corner_y, g);
-  if ((fl >> 1) && owner) link_force(a.g, a.partial2, x, y, fl, g, w1, a.p);
+  if ((fl >> 1) && owner) link_force(a.g, partial, x, y, fl, g, w1, a.p);
   collide(g, a.p, out, b);
   bad |= b && owner;
 }
@@ -867,7 +870,7 @@ __device__ __forceinline__ void general_wave(const StepArgs& a, int segment, int
     if (r > y0) {
       const int y2 = r - 1;
       float out[9];
-      second_update(a, x, y2, col_ok, out_col, w0, w1, w2, out, bad2);
+      second_update(a, a.partial2, x, y2, col_ok, out_col, w0, w1, w2, out, bad2);
       if (out_col) store9<NT>(a.B, P, (uint32_t)y2 * Wp + (uint32_t)x, out);
     }
   }
@@ -897,6 +900,152 @@ __global__ __launch_bounds__(256) void step2_kernel(StepArgs a) {
   }
   const int wave = (b - gen_blocks) * 4 + w;
   if (wave < a.t.ntx * a.t.nty) bulk_wave<NT, H>(a, wave % a.t.ntx, wave / a.t.ntx);
+}
+
+// ---------------------------------------------------------------- three steps
+// The same scheme one level deeper: each wave's 64 lanes hold columns
+// xs-2 .. xs+61 and output the kStrip3 = 60 columns xs .. xs+59; f*(t+1)
+// is computed from memory on the segment's rows widened by two on each side,
+// f*(t+2) from it on rows widened by one, f*(t+3) on the segment's rows, and
+// only f*(t+3) is stored.
+
+// Pulled values of a node from the level below, held as rows above (wa), at
+// (wb) and below (wc) the node, x-neighbours in the adjacent lanes.
+__device__ __forceinline__ void pull_rows(const float (&wa)[9], const float (&wb)[9], const float (&wc)[9],
+                                          float (&c)[9]) {
+  c[0] = wb[0];
+  c[1] = from_left(wb[1]);
+  c[2] = wa[2];
+  c[3] = from_right(wb[3]);
+  c[4] = wc[4];
+  c[5] = from_left(wa[5]);
+  c[6] = from_right(wa[6]);
+  c[7] = from_right(wc[7]);
+  c[8] = from_left(wc[8]);
+}
+
+// Interior segments, H rows; loads run AHEAD rows ahead of the first level
+// (all of them first when they fit), outputs are stored at the end.
+template <bool NT, int H>
+__device__ __forceinline__ void bulk_wave3(const StepArgs& a, int strip, int seg) {
+  const int lane = (int)(threadIdx.x & 63);
+  if (!interior_segment(a.g, a.t, a.p.x_periodic, strip, seg)) return;
+  const int xs = strip_start(a.g, a.t, a.p.x_periodic, strip);
+  const int y0 = seg * H;
+  const int x = xs - 2 + lane;
+  const bool out_col = lane >= 2 && lane <= kStrip3 + 1;
+  constexpr int N1 = H + 4;  // first-level rows y0-2 .. y0+H+1
+  constexpr int AHEAD = N1 <= 8 ? N1 : 3, R = AHEAD + 1;
+  float w1[3][9], w2[3][9], pre[R][9], out[H][9];
+#pragma unroll
+  for (int i = 0; i < AHEAD; ++i) load_pull(a, x, y0 - 2 + i, pre[i]);
+  bool bad1 = false, bad2 = false, bad3 = false;
+#pragma unroll
+  for (int i = 0; i < N1; ++i) {  // f*(t+1) of row y0-2+i
+    if (i + AHEAD < N1) load_pull(a, x, y0 - 2 + i + AHEAD, pre[(i + AHEAD) % R]);
+    bool b1 = false;
+    collide(pre[i % R], a.p, w1[i % 3], b1);
+    if (i >= 2 && i < H + 2) bad1 |= b1;
+    if (i >= 2) {  // f*(t+2) of row y0-3+i
+      float c[9];
+      pull_rows(w1[(i + 1) % 3], w1[(i + 2) % 3], w1[i % 3], c);
+      bool b2 = false;
+      collide(c, a.p, w2[i % 3], b2);
+      if (i >= 3 && i < H + 3) bad2 |= b2;
+    }
+    if (i >= 4) {  // f*(t+3) of row y0-4+i
+      float c[9];
+      pull_rows(w2[(i + 1) % 3], w2[(i + 2) % 3], w2[i % 3], c);
+      collide(c, a.p, out[i - 4], bad3);
+    }
+  }
+  report_bad(a.bad, bad1 && out_col, a.slot);
+  report_bad(a.bad, bad2 && out_col, a.slot + 1);
+  report_bad(a.bad, bad3 && out_col, a.slot + 2);
+  if (!out_col) return;
+  const uint32_t P = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
+#pragma unroll
+  for (int j = 0; j < H; ++j) store9<NT>(a.B, P, (uint32_t)(y0 + j) * Wp + (uint32_t)x, out[j]);
+}
+
+// SUB rows (fewer at the segment's or the lattice's end) of a segment that
+// is not interior, with the boundary code on every level; a rolled loop like
+// general_wave's.
+template <bool NT, int SUB>
+__device__ __forceinline__ void general_wave3(const StepArgs& a, int segment, int sub) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int S = a.t.ntx, H = a.t.tile_y;
+  const int strip = segment % S, seg = segment / S;
+  const int nx = a.g.nx, ny = a.g.ny;
+  const bool xper = a.p.x_periodic, yper = a.p.wall == kWallPeriodic;
+  const int xs = strip_start(a.g, a.t, xper, strip);
+  const int y0 = seg * H + sub * SUB;
+  if (y0 >= ny) return;
+  const int y1 = min(min(y0 + SUB, seg * H + H), ny);
+  const int ux = xs - 2 + lane;  // column before wrapping
+  const int x = xper ? ((ux % nx) + nx) % nx : ux;
+  const bool col_ok = xper || (ux >= 0 && ux < nx);
+  const bool out_col = lane >= 2 && lane <= kStrip3 + 1 && ux >= 0 && ux < nx;
+  const uint32_t P = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
+  float a0[9], a1[9], a2[9], b0[9], b1[9], b2[9], pre[9], pre1[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) a0[k] = a1[k] = a2[k] = b0[k] = b1[k] = b2[k] = 0.0f;
+  auto row_of = [&](int r) { return yper ? (r < 0 ? r + ny : (r >= ny ? r - ny : r)) : r; };
+  auto row_ok = [&](int r) { return yper || (r >= 0 && r < ny); };
+  prefetch_bulk(a, x, row_of(y0 - 2), pre);
+  prefetch_bulk(a, x, row_of(y0 - 1), pre1);
+  bool bad1 = false, bad2 = false, bad3 = false;
+#pragma unroll 1
+  for (int r = y0 - 2; r <= y1 + 1; ++r) {
+    float nxt[9];
+    prefetch_bulk(a, x, row_of(r + 2), nxt);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      a0[k] = a1[k];
+      a1[k] = a2[k];
+    }
+    // f*(t+1) of row r
+    first_update(a, x, row_of(r), col_ok && row_ok(r), out_col && r >= y0 && r < y1, pre, a2, bad1);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      pre[k] = pre1[k];
+      pre1[k] = nxt[k];
+    }
+    if (r >= y0) {  // f*(t+2) of row r-1
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        b0[k] = b1[k];
+        b1[k] = b2[k];
+      }
+      const int q = r - 1;
+      second_update(a, a.partial2, x, row_of(q), col_ok && row_ok(q), out_col && q >= y0 && q < y1, a0, a1, a2,
+                    b2, bad2);
+    }
+    if (r >= y0 + 2) {  // f*(t+3) of row r-2
+      const int y3 = r - 2;
+      float out[9];
+      second_update(a, a.partial3, x, y3, col_ok, out_col, b0, b1, b2, out, bad3);
+      if (out_col) store9<NT>(a.B, P, (uint32_t)y3 * Wp + (uint32_t)x, out);
+    }
+  }
+  report_bad(a.bad, bad1, a.slot);
+  report_bad(a.bad, bad2, a.slot + 1);
+  report_bad(a.bad, bad3, a.slot + 2);
+}
+
+// One launch, three steps; blocks as in step2_kernel.
+template <bool NT, int H, int SUB>
+__global__ __launch_bounds__(256) void step3_kernel(StepArgs a) {
+  constexpr int per = (H + SUB - 1) / SUB;
+  const int gen_blocks = (a.n_gen * per + 3) / 4;
+  const int b = (int)blockIdx.x, w = (int)(threadIdx.x >> 6);
+  if (b < gen_blocks) {
+    const int wave = b * 4 + w;
+    if (wave < a.n_gen * per) general_wave3<NT, SUB>(a, a.gen[wave / per], wave % per);
+    return;
+  }
+  const int wave = (b - gen_blocks) * 4 + w;
+  if (wave < a.t.ntx * a.t.nty) bulk_wave3<NT, H>(a, wave % a.t.ntx, wave / a.t.ntx);
 }
 
 // One step of a whole ensemble: block b processes tile tiles[b] = (case,
@@ -1091,6 +1240,12 @@ constexpr Variant kVariants[] = {
     {"t2_h16", kStrip2, 16, 1, 0, 0, 2, 2},
     {"t2_h4_s4", kStrip2, 4, 1, 0, 0, 2, 4},
     {"t2_h6_s4", kStrip2, 6, 1, 0, 0, 2, 4},
+    {"t3_h4_s4", kStrip3, 4, 1, 0, 0, 3, 4},
+    {"t3_h6_s4", kStrip3, 6, 1, 0, 0, 3, 4},
+    {"t3_h8_s4", kStrip3, 8, 1, 0, 0, 3, 4},
+    {"t3_h12_s4", kStrip3, 12, 1, 0, 0, 3, 4},
+    {"t3_h16_s4", kStrip3, 16, 1, 0, 0, 3, 4},
+    {"t3_h8_s8", kStrip3, 8, 1, 0, 0, 3, 8},
 };
 
 }  // namespace
@@ -1104,9 +1259,15 @@ const Variant& variant(int v) { return kVariants[v - 1]; }
 // own band of rows is fastest (10-25 % over the plain order at 86 k-800 k
 // nodes; the plain order wins once the lattice streams from HBM).  Boundary
 // waves of 4 rows gain 2-17 % from 2.8 M nodes on and lose 25 % at 1.4 M,
-// where the launch lasts about as long as one such wave.
+// where the launch lasts about as long as one such wave.  Three steps per
+// launch gain 29 % at 5.5 M nodes and 45 % at 22 M, 5 % at 2.8 M (an
+// x-periodic slab), and lose 20 % at 1.4 M.  Their boundary waves take 8
+// rows where the launch is long (22 M nodes) or the boundary strips are
+// many (the slab: 2 of 14), 4 rows in between (5.5 M: 4 % faster).
 int default_variant(int64_t nodes) {
-  const char* want = nodes >= ((int64_t)1 << 21) ? "t2_h4_s4"
+  const char* want = nodes >= ((int64_t)1 << 24)   ? "t3_h8_s8"
+                     : nodes >= ((int64_t)1 << 22) ? "t3_h8_s4"
+                     : nodes >= ((int64_t)1 << 21) ? "t3_h8_s8"
                      : nodes >= ((int64_t)1 << 20) ? "t2_h4"
                                                    : "v1_ty1_xcd";
   for (int v = 1; v <= num_variants(); ++v)
@@ -1161,6 +1322,24 @@ hipError_t launch_step(const StepArgs& a, int v, hipStream_t s) {
     LBM_T2(false, 4, 4)
     LBM_T2(false, 6, 4)
 #undef LBM_T2
+    return hipErrorInvalidValue;
+  }
+  if (var.steps == 3) {
+    const int per = (var.tile_y + var.sub - 1) / var.sub;
+    const int blocks = (a.n_gen * per + 3) / 4 + (a.t.ntx * a.t.nty + 3) / 4;
+    const dim3 grid((unsigned)blocks), block(256);
+#define LBM_T3(NT, H, SUB)                                                 \
+  if (var.nontemporal == NT && var.tile_y == H && var.sub == SUB) {        \
+    hipLaunchKernelGGL((step3_kernel<NT, H, SUB>), grid, block, 0, s, a);  \
+    return hipGetLastError();                                              \
+  }
+    LBM_T3(false, 4, 4)
+    LBM_T3(false, 6, 4)
+    LBM_T3(false, 8, 4)
+    LBM_T3(false, 12, 4)
+    LBM_T3(false, 16, 4)
+    LBM_T3(false, 8, 8)
+#undef LBM_T3
     return hipErrorInvalidValue;
   }
   const dim3 grid((unsigned)(a.t.ntx * a.t.nty)), block(256);

@@ -83,11 +83,12 @@ def test_c1_force_trace_2000_steps():
 
 
 @pytest.mark.parametrize("name", ["cyl_d80", "cyl_d160", "slab_d160_of8"])
-def test_full_size_two_steps_all_nodes(name):
+def test_full_size_multi_step_all_nodes(name):
     """The benchmark's lattices in the benchmark's launch configuration:
-    two steps from a disturbed state, every node against the oracle."""
+    three steps from a disturbed state (one launch of the three-step kernel
+    by default on all three lattices), every node against the oracle."""
     kw = dict(WORKLOADS[name])
-    lat, o, (fx, fy, _, _), (ofx, ofy) = run_both(kw, 2, seed=160, amp=0.02)
+    lat, o, (fx, fy, _, _), (ofx, ofy) = run_both(kw, 3, seed=160, amp=0.02)
     f = lat.get_populations(np.float64)
     of = o.get_fstar()
     solid = oracle.digitise(oracle.OracleParams(**_oracle_kwargs(kw)))
@@ -201,7 +202,7 @@ def test_device_buffers_round_trip():
 
 
 def test_graph_replay_matches_plain_launches():
-    """lbm_step replays captured 64-step graphs; several replays with eager
+    """lbm_step replays captured 96-step graphs; several replays with eager
     work in between must match plain launches bit for bit."""
     kw = dict(channel(6, u=0.06), tau=0.6, wall=lbm.WALL_NEBB)
     a = lbm.Lattice(lbm.make_params(**kw))
@@ -219,7 +220,7 @@ def test_graph_replay_matches_plain_launches():
 
 
 # ------------------------------------------- two steps per launch
-TWO_STEP = [v for v in range(1, lbm.num_variants() + 1) if lbm.variant_name(v).startswith("t2_")]
+TWO_STEP = [v for v in range(1, lbm.num_variants() + 1) if lbm.variant_name(v)[:3] in ("t2_", "t3_")]
 
 
 def _two_step_cases():
@@ -242,12 +243,12 @@ def _two_step_cases():
 
 @pytest.mark.parametrize("case", range(len(_two_step_cases())))
 def test_two_step_variants_match_one_step_bitwise(case):
-    """The two-step kernels (f*(t+1) kept in registers) give the one-step
-    kernel's populations and force history bit for bit, for every wall and
-    outlet treatment, periodic boxes down to 3 x 3, odd step counts (the last
-    step then runs alone) and graph replay."""
+    """The two- and three-step kernels (f*(t+1), f*(t+2) kept in registers)
+    give the one-step kernel's populations and force history bit for bit, for
+    every wall and outlet treatment, periodic boxes down to 3 x 3, step
+    counts that leave single steps (which then run alone) and graph replay."""
     kw = _two_step_cases()[case]
-    steps = 131  # two 64-step graphs, then a pair and a single step
+    steps = 131  # a 96-step graph, then plain launches of every size
     seed = 500 + case
     ref = _run_gpu(kw, steps, 0, seed)
     for v in TWO_STEP:
@@ -260,16 +261,17 @@ def test_two_step_variants_match_one_step_bitwise(case):
 
 
 def test_default_variant_follows_the_lattice_size():
-    """Two steps per launch from 2^20 nodes on (boundary waves of 4 rows from
-    2^21), one below (cached stores, XCD bands); variant 0 restores the
-    default."""
+    """One step per launch below 2^20 nodes (cached stores, XCD bands), two
+    from 2^20, three from 2^21 (boundary waves of 8 rows, of 4 between 2^22
+    and 2^24); variant 0 restores the default."""
     small = lbm.Lattice(lbm.make_params(**WORKLOADS["cyl_d10"]))
     big = lbm.Lattice(lbm.make_params(**WORKLOADS["cyl_d40"]))
     assert lbm.variant_name(small.variant) == "v1_ty1_xcd"
     assert lbm.variant_name(big.variant) == "t2_h4"
-    bigger = lbm.Lattice(lbm.make_params(**WORKLOADS["slab_d160_of8"]))
-    assert lbm.variant_name(bigger.variant) == "t2_h4_s4"
-    bigger.close()
+    for name, want in (("slab_d160_of8", "t3_h8_s8"), ("cyl_d80", "t3_h8_s4"), ("cyl_d160", "t3_h8_s8")):
+        lat = lbm.Lattice(lbm.make_params(**WORKLOADS[name]))
+        assert lbm.variant_name(lat.variant) == want, name
+        lat.close()
     big.set_variant(1)
     assert big.variant == 1
     big.set_variant(0)
