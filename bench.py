@@ -160,7 +160,7 @@ def main():
     fluid = nodes - lbm.geometry(p)[1]
 
     vname = lbm.variant_name(lat.variant)
-    steps_per_launch = {"t2": 2, "t3": 3}.get(vname[:2], 1)
+    steps_per_launch = {"t2": 2, "t3": 3, "t4": 4}.get(vname[:2], 1)
     launch_ms = ms_per_step * steps_per_launch
     achieved = BYTES_PER_NODE * nodes * steps_per_launch / (launch_ms * 1e-3) / 1e9
     traffic = stored_traffic(args.workload, args.collision, vname)
@@ -171,7 +171,7 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / PEAK_HBM_GBS, 4),
         "traffic": traffic,
-        "kernel": {2: "step2_kernel", 3: "step3_kernel"}.get(steps_per_launch, "step_kernel"),
+        "kernel": {1: "step_kernel", 2: "step2_kernel"}.get(steps_per_launch, "multistep_kernel"),
         "steps_per_launch": steps_per_launch,
         "launch_us": round(launch_ms * 1e3, 2),
         "algorithmic_bytes_per_launch": BYTES_PER_NODE * nodes * steps_per_launch,

@@ -36,8 +36,8 @@ def main():
     ap.add_argument("--collision", default="bgk")
     ap.add_argument("--variant", required=True)
     a = ap.parse_args()
-    steps = {"t2": 2, "t3": 3}.get(a.variant[:2], 1)
-    kname = {2: "step2_kernel", 3: "step3_kernel"}.get(steps, "step_kernel<")
+    steps = {"t2": 2, "t3": 3, "t4": 4}.get(a.variant[:2], 1)
+    kname = {1: "step_kernel<", 2: "step2_kernel"}.get(steps, "multistep_kernel")
     w = WORKLOADS[a.workload]
     nodes = w["nx"] * w["ny"]
     copy_bytes = 9 * nodes * 4

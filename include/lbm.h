@@ -190,13 +190,13 @@ lbm_status lbm_shedding_stats(const double* cd, const double* cl, int64_t n, dou
 
 /* Kernel selection for measurement and autotuning.  Valid variants are
  * 1..lbm_num_variants(); variant 0 selects the context's default.  The result
- * is bit-identical for every variant.  Variants named "t2_*" ("t3_*") advance
- * two (three) time steps per launch and keep the intermediate populations in
- * registers, so one launch reads and writes each population once for two
- * (three) node updates; the steps left over (a remainder of n, or the steps
- * of a learned closure, which "t3_*" variants run one at a time) run the
+ * is bit-identical for every variant.  Variants named "tS_*" (S = 2, 3, 4)
+ * advance S time steps per launch and keep the intermediate populations in
+ * registers, so one launch reads and writes each population once for S node
+ * updates; the steps left over (a remainder of n, or the steps of a learned
+ * closure, which "t3_*" and "t4_*" variants run one at a time) run the
  * one-step kernel.  The default of
- * a new context is "t3_h8_s8" from 2^24 nodes, "t3_h8_s4" from 2^22,
+ * a new context is "t4_h8_s8" from 2^24 nodes, "t4_h12_s4" from 2^22,
  * "t3_h8_s8" from 2^21, "t2_h4" from 2^20 and the one-step "v1_ty1_xcd"
  * (cached stores, each XCD on its own band of rows) below ("_sN": segments
  * that need the boundary code run in pieces of N rows).  lbm_get_variant

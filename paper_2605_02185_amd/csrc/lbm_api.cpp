@@ -503,16 +503,17 @@ bool pairable(const lbm_ctx* c) {
   return !c->mlp || (c->closure_interval % 2 == 0 && (c->step + 1) % c->closure_interval != 0);
 }
 
-// Steps of the next launch, with `left` steps still to go: the variant's two
-// or three when they fit (three only without a learned closure), else one.
+// Steps of the next launch, with `left` steps still to go: the variant's two,
+// three or four when they fit (more than two only without a learned
+// closure), else one.
 int group(const lbm_ctx* c, int64_t left) {
   const int s = lbm::variant(c->variant).steps;
-  if (s == 3 && left >= 3 && !c->mlp && c->pending + 3 <= lbm::kRing) return 3;
+  if (s >= 3 && left >= s && !c->mlp && c->pending + s <= lbm::kRing) return s;
   if (s == 2 && left >= 2 && pairable(c)) return 2;
   return 1;
 }
 
-// Enqueues k = 1, 2 or 3 steps (k > 1 only as group() allows) on stream s,
+// Enqueues k = 1 to 4 steps (k > 1 only as group() allows) on stream s,
 // buffers by c->cur and ring slots from c->pending, and advances the
 // host-side bookkeeping; folds the ring when it is full.  One launch always
 // moves the state from buf[cur] to buf[cur ^ 1].
@@ -529,7 +530,8 @@ lbm_status enqueue_step(lbm_ctx* c, hipStream_t s, int k = 1) {
   int v = c->variant;
   if (k >= 2) {
     a.partial2 = a.partial + slots_of(c);
-    a.partial3 = k == 3 ? a.partial2 + slots_of(c) : nullptr;
+    a.partial3 = k >= 3 ? a.partial2 + slots_of(c) : nullptr;
+    a.partial4 = k >= 4 ? a.partial3 + slots_of(c) : nullptr;
     a.gen = c->d_gen;
     a.n_gen = c->n_gen;
   } else if (lbm::variant(v).steps != 1) {

@@ -65,13 +65,14 @@ struct Tiling {
   int remap_xcd;         // block-to-tile map: 0 plain, 1 XCD bands, 2 XCD-interleaved rows
 };
 
-// Two or three steps per launch: each wave owns tile_x output columns (its
+// Two to four steps per launch: each wave owns tile_x output columns (its
 // 64 lanes hold one more column on either side per step beyond the first:
-// kStrip2 = 62 for two steps, kStrip3 = 60 for three) of one segment of
-// tile_y rows.  Without x-periodicity the strips are aligned to the right
+// kStrip2 = 62 for two steps, kStrip3 = 60 for three, kStrip4 = 58 for four)
+// of one segment of tile_y rows.  Without x-periodicity the strips are aligned to the right
 // edge.
 constexpr int kStrip2 = 62;
 constexpr int kStrip3 = 60;
+constexpr int kStrip4 = 58;
 
 __host__ __device__ inline int strip_halo(const Tiling& t) { return (64 - t.tile_x) / 2; }
 
@@ -100,7 +101,8 @@ struct StepArgs {
   Tiling t;
   double2* partial;             // this step's force contributions [n_link_nodes]
   double2* partial2;            // the second step's, for kernels that take two or three steps
-  double2* partial3;            // the third step's, for kernels that take three
+  double2* partial3;            // the third step's, for kernels that take three or four
+  double2* partial4;            // the fourth step's, for kernels that take four
   const int* gen;               // multi-step launches: segments (seg * ntx + strip) that are not interior
   int n_gen;
   const float* closure;         // learned-closure residuals [boundary node][3], or null
@@ -129,7 +131,7 @@ struct Variant {
                        // variants the output columns per wave and rows per segment
   int vx;              // consecutive nodes per lane on the bulk path
   int remap_xcd, nontemporal;
-  int steps;           // time steps per launch (1, or 2-3 with the intermediate states in registers)
+  int steps;           // time steps per launch (1, or 2-4 with the intermediate states in registers)
   int sub;             // two-step: rows per wave of the segments that need the boundary code
 };
 

@@ -902,12 +902,13 @@ __global__ __launch_bounds__(256) void step2_kernel(StepArgs a) {
   if (wave < a.t.ntx * a.t.nty) bulk_wave<NT, H>(a, wave % a.t.ntx, wave / a.t.ntx);
 }
 
-// ---------------------------------------------------------------- three steps
-// The same scheme one level deeper: each wave's 64 lanes hold columns
-// xs-2 .. xs+61 and output the kStrip3 = 60 columns xs .. xs+59; f*(t+1)
-// is computed from memory on the segment's rows widened by two on each side,
-// f*(t+2) from it on rows widened by one, f*(t+3) on the segment's rows, and
-// only f*(t+3) is stored.
+// ------------------------------------------------------- three or four steps
+// The same scheme S - 1 levels deeper (S = 3 or 4 steps per launch): each
+// wave's 64 lanes hold its 64 - 2(S-1) output columns (kStrip3 = 60,
+// kStrip4 = 58) and S - 1 more on either side; f*(t+1) is computed from
+// memory on the segment's rows widened by S - 1 on each side, each further
+// level from the one below it in registers on rows widened by one less, and
+// only f*(t+S) is stored.
 
 // Pulled values of a node from the level below, held as rows above (wa), at
 // (wb) and below (wc) the node, x-neighbours in the adjacent lanes.
@@ -924,44 +925,56 @@ __device__ __forceinline__ void pull_rows(const float (&wa)[9], const float (&wb
   c[8] = from_left(wc[8]);
 }
 
-// Interior segments, H rows; loads run AHEAD rows ahead of the first level
-// (all of them first when they fit), outputs are stored at the end.
-template <bool NT, int H>
-__device__ __forceinline__ void bulk_wave3(const StepArgs& a, int strip, int seg) {
+// Force contributions of level l (1-based) of a multi-step launch.
+__device__ __forceinline__ double2* level_partial(const StepArgs& a, int l) {
+  return l == 1 ? a.partial : l == 2 ? a.partial2 : l == 3 ? a.partial3 : a.partial4;
+}
+
+// Interior segments, H rows.  Iteration i computes level 1 on row
+// y0 - h + i from memory and level l on row y0 - h + i - (l - 1) from the
+// rows of level l - 1 made in iterations i - 2 .. i; loads run AHEAD rows
+// ahead of level 1 (all of them first when they fit), outputs are stored at
+// the end.
+template <bool NT, int H, int S>
+__device__ __forceinline__ void bulk_wave_n(const StepArgs& a, int strip, int seg) {
+  constexpr int h = S - 1, W = 64 - 2 * h;
   const int lane = (int)(threadIdx.x & 63);
   if (!interior_segment(a.g, a.t, a.p.x_periodic, strip, seg)) return;
   const int xs = strip_start(a.g, a.t, a.p.x_periodic, strip);
   const int y0 = seg * H;
-  const int x = xs - 2 + lane;
-  const bool out_col = lane >= 2 && lane <= kStrip3 + 1;
-  constexpr int N1 = H + 4;  // first-level rows y0-2 .. y0+H+1
+  const int x = xs - h + lane;
+  const bool out_col = lane >= h && lane < h + W;
+  constexpr int N1 = H + 2 * h;  // first-level rows y0-h .. y0+H+h-1
   constexpr int AHEAD = N1 <= 8 ? N1 : 3, R = AHEAD + 1;
-  float w1[3][9], w2[3][9], pre[R][9], out[H][9];
+  float w[S - 1][3][9], pre[R][9], out[H][9];
 #pragma unroll
-  for (int i = 0; i < AHEAD; ++i) load_pull(a, x, y0 - 2 + i, pre[i]);
-  bool bad1 = false, bad2 = false, bad3 = false;
+  for (int i = 0; i < AHEAD; ++i) load_pull(a, x, y0 - h + i, pre[i]);
+  bool bad[S];
 #pragma unroll
-  for (int i = 0; i < N1; ++i) {  // f*(t+1) of row y0-2+i
-    if (i + AHEAD < N1) load_pull(a, x, y0 - 2 + i + AHEAD, pre[(i + AHEAD) % R]);
+  for (int l = 0; l < S; ++l) bad[l] = false;
+#pragma unroll
+  for (int i = 0; i < N1; ++i) {
+    if (i + AHEAD < N1) load_pull(a, x, y0 - h + i + AHEAD, pre[(i + AHEAD) % R]);
     bool b1 = false;
-    collide(pre[i % R], a.p, w1[i % 3], b1);
-    if (i >= 2 && i < H + 2) bad1 |= b1;
-    if (i >= 2) {  // f*(t+2) of row y0-3+i
+    collide(pre[i % R], a.p, w[0][i % 3], b1);
+    if (i >= h && i < h + H) bad[0] |= b1;
+#pragma unroll
+    for (int l = 2; l <= S; ++l) {
+      if (i < 2 * (l - 1)) continue;
       float c[9];
-      pull_rows(w1[(i + 1) % 3], w1[(i + 2) % 3], w1[i % 3], c);
-      bool b2 = false;
-      collide(c, a.p, w2[i % 3], b2);
-      if (i >= 3 && i < H + 3) bad2 |= b2;
-    }
-    if (i >= 4) {  // f*(t+3) of row y0-4+i
-      float c[9];
-      pull_rows(w2[(i + 1) % 3], w2[(i + 2) % 3], w2[i % 3], c);
-      collide(c, a.p, out[i - 4], bad3);
+      pull_rows(w[l - 2][(i + 1) % 3], w[l - 2][(i + 2) % 3], w[l - 2][i % 3], c);
+      if (l < S) {
+        bool b = false;
+        collide(c, a.p, w[l - 1][i % 3], b);
+        const int q = i - h - (l - 1);  // row - y0
+        if (q >= 0 && q < H) bad[l - 1] |= b;
+      } else {
+        collide(c, a.p, out[i - 2 * h], bad[S - 1]);
+      }
     }
   }
-  report_bad(a.bad, bad1 && out_col, a.slot);
-  report_bad(a.bad, bad2 && out_col, a.slot + 1);
-  report_bad(a.bad, bad3 && out_col, a.slot + 2);
+#pragma unroll
+  for (int l = 0; l < S; ++l) report_bad(a.bad, bad[l] && out_col, a.slot + l);
   if (!out_col) return;
   const uint32_t P = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
 #pragma unroll
@@ -970,82 +983,92 @@ __device__ __forceinline__ void bulk_wave3(const StepArgs& a, int strip, int seg
 
 // SUB rows (fewer at the segment's or the lattice's end) of a segment that
 // is not interior, with the boundary code on every level; a rolled loop like
-// general_wave's.
-template <bool NT, int SUB>
-__device__ __forceinline__ void general_wave3(const StepArgs& a, int segment, int sub) {
+// general_wave's over the first-level rows r, each level l > 1 following on
+// row r - (l - 1).
+template <bool NT, int SUB, int S>
+__device__ __forceinline__ void general_wave_n(const StepArgs& a, int segment, int sub) {
+  constexpr int h = S - 1, W = 64 - 2 * h;
   const int lane = (int)(threadIdx.x & 63);
-  const int S = a.t.ntx, H = a.t.tile_y;
-  const int strip = segment % S, seg = segment / S;
+  const int St = a.t.ntx, H = a.t.tile_y;
+  const int strip = segment % St, seg = segment / St;
   const int nx = a.g.nx, ny = a.g.ny;
   const bool xper = a.p.x_periodic, yper = a.p.wall == kWallPeriodic;
   const int xs = strip_start(a.g, a.t, xper, strip);
   const int y0 = seg * H + sub * SUB;
   if (y0 >= ny) return;
   const int y1 = min(min(y0 + SUB, seg * H + H), ny);
-  const int ux = xs - 2 + lane;  // column before wrapping
+  const int ux = xs - h + lane;  // column before wrapping
   const int x = xper ? ((ux % nx) + nx) % nx : ux;
   const bool col_ok = xper || (ux >= 0 && ux < nx);
-  const bool out_col = lane >= 2 && lane <= kStrip3 + 1 && ux >= 0 && ux < nx;
+  const bool out_col = lane >= h && lane < h + W && ux >= 0 && ux < nx;
   const uint32_t P = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
-  float a0[9], a1[9], a2[9], b0[9], b1[9], b2[9], pre[9], pre1[9];
+  float lv[S - 1][3][9], pre[9], pre1[9];  // rows q-1, q, q+1 of each level below the last
 #pragma unroll
-  for (int k = 0; k < 9; ++k) a0[k] = a1[k] = a2[k] = b0[k] = b1[k] = b2[k] = 0.0f;
+  for (int l = 0; l < S - 1; ++l)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) lv[l][j][k] = 0.0f;
   auto row_of = [&](int r) { return yper ? (r < 0 ? r + ny : (r >= ny ? r - ny : r)) : r; };
   auto row_ok = [&](int r) { return yper || (r >= 0 && r < ny); };
-  prefetch_bulk(a, x, row_of(y0 - 2), pre);
-  prefetch_bulk(a, x, row_of(y0 - 1), pre1);
-  bool bad1 = false, bad2 = false, bad3 = false;
+  prefetch_bulk(a, x, row_of(y0 - h), pre);
+  prefetch_bulk(a, x, row_of(y0 - h + 1), pre1);
+  bool bad[S];
+#pragma unroll
+  for (int l = 0; l < S; ++l) bad[l] = false;
 #pragma unroll 1
-  for (int r = y0 - 2; r <= y1 + 1; ++r) {
+  for (int r = y0 - h; r <= y1 + h - 1; ++r) {
     float nxt[9];
     prefetch_bulk(a, x, row_of(r + 2), nxt);
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      a0[k] = a1[k];
-      a1[k] = a2[k];
+      lv[0][0][k] = lv[0][1][k];
+      lv[0][1][k] = lv[0][2][k];
     }
-    // f*(t+1) of row r
-    first_update(a, x, row_of(r), col_ok && row_ok(r), out_col && r >= y0 && r < y1, pre, a2, bad1);
+    // level 1 (f*(t+1)) of row r
+    first_update(a, x, row_of(r), col_ok && row_ok(r), out_col && r >= y0 && r < y1, pre, lv[0][2], bad[0]);
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       pre[k] = pre1[k];
       pre1[k] = nxt[k];
     }
-    if (r >= y0) {  // f*(t+2) of row r-1
 #pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        b0[k] = b1[k];
-        b1[k] = b2[k];
+    for (int l = 2; l <= S; ++l) {
+      if (r < y0 - h + 2 * (l - 1)) continue;
+      const int q = r - (l - 1);  // level l of row q
+      if (l < S) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          lv[l - 1][0][k] = lv[l - 1][1][k];
+          lv[l - 1][1][k] = lv[l - 1][2][k];
+        }
+        second_update(a, level_partial(a, l), x, row_of(q), col_ok && row_ok(q), out_col && q >= y0 && q < y1,
+                      lv[l - 2][0], lv[l - 2][1], lv[l - 2][2], lv[l - 1][2], bad[l - 1]);
+      } else {
+        float out[9];
+        second_update(a, level_partial(a, l), x, q, col_ok, out_col, lv[l - 2][0], lv[l - 2][1], lv[l - 2][2], out,
+                      bad[S - 1]);
+        if (out_col) store9<NT>(a.B, P, (uint32_t)q * Wp + (uint32_t)x, out);
       }
-      const int q = r - 1;
-      second_update(a, a.partial2, x, row_of(q), col_ok && row_ok(q), out_col && q >= y0 && q < y1, a0, a1, a2,
-                    b2, bad2);
-    }
-    if (r >= y0 + 2) {  // f*(t+3) of row r-2
-      const int y3 = r - 2;
-      float out[9];
-      second_update(a, a.partial3, x, y3, col_ok, out_col, b0, b1, b2, out, bad3);
-      if (out_col) store9<NT>(a.B, P, (uint32_t)y3 * Wp + (uint32_t)x, out);
     }
   }
-  report_bad(a.bad, bad1, a.slot);
-  report_bad(a.bad, bad2, a.slot + 1);
-  report_bad(a.bad, bad3, a.slot + 2);
+#pragma unroll
+  for (int l = 0; l < S; ++l) report_bad(a.bad, bad[l], a.slot + l);
 }
 
-// One launch, three steps; blocks as in step2_kernel.
-template <bool NT, int H, int SUB>
-__global__ __launch_bounds__(256) void step3_kernel(StepArgs a) {
+// One launch, S steps; blocks as in step2_kernel.
+template <bool NT, int H, int SUB, int S>
+__global__ __launch_bounds__(256) void multistep_kernel(StepArgs a) {
   constexpr int per = (H + SUB - 1) / SUB;
   const int gen_blocks = (a.n_gen * per + 3) / 4;
   const int b = (int)blockIdx.x, w = (int)(threadIdx.x >> 6);
   if (b < gen_blocks) {
     const int wave = b * 4 + w;
-    if (wave < a.n_gen * per) general_wave3<NT, SUB>(a, a.gen[wave / per], wave % per);
+    if (wave < a.n_gen * per) general_wave_n<NT, SUB, S>(a, a.gen[wave / per], wave % per);
     return;
   }
   const int wave = (b - gen_blocks) * 4 + w;
-  if (wave < a.t.ntx * a.t.nty) bulk_wave3<NT, H>(a, wave % a.t.ntx, wave / a.t.ntx);
+  if (wave < a.t.ntx * a.t.nty) bulk_wave_n<NT, H, S>(a, wave % a.t.ntx, wave / a.t.ntx);
 }
 
 // One step of a whole ensemble: block b processes tile tiles[b] = (case,
@@ -1244,8 +1267,11 @@ constexpr Variant kVariants[] = {
     {"t3_h6_s4", kStrip3, 6, 1, 0, 0, 3, 4},
     {"t3_h8_s4", kStrip3, 8, 1, 0, 0, 3, 4},
     {"t3_h12_s4", kStrip3, 12, 1, 0, 0, 3, 4},
-    {"t3_h16_s4", kStrip3, 16, 1, 0, 0, 3, 4},
     {"t3_h8_s8", kStrip3, 8, 1, 0, 0, 3, 8},
+    {"t4_h8_s4", kStrip4, 8, 1, 0, 0, 4, 4},
+    {"t4_h8_s8", kStrip4, 8, 1, 0, 0, 4, 8},
+    {"t4_h12_s4", kStrip4, 12, 1, 0, 0, 4, 4},
+    {"t4_h12_s12", kStrip4, 12, 1, 0, 0, 4, 12},
 };
 
 }  // namespace
@@ -1261,12 +1287,13 @@ const Variant& variant(int v) { return kVariants[v - 1]; }
 // waves of 4 rows gain 2-17 % from 2.8 M nodes on and lose 25 % at 1.4 M,
 // where the launch lasts about as long as one such wave.  Three steps per
 // launch gain 29 % at 5.5 M nodes and 45 % at 22 M, 5 % at 2.8 M (an
-// x-periodic slab), and lose 20 % at 1.4 M.  Their boundary waves take 8
+// x-periodic slab), and lose 20 % at 1.4 M; four steps gain another 16 % at
+// 22 M and 6 % at 5.5 M but lose 5 % on the slab.  Boundary waves take 8
 // rows where the launch is long (22 M nodes) or the boundary strips are
-// many (the slab: 2 of 14), 4 rows in between (5.5 M: 4 % faster).
+// many (the slab: 2 of 14), 4 rows in between (5.5 M).
 int default_variant(int64_t nodes) {
-  const char* want = nodes >= ((int64_t)1 << 24)   ? "t3_h8_s8"
-                     : nodes >= ((int64_t)1 << 22) ? "t3_h8_s4"
+  const char* want = nodes >= ((int64_t)1 << 24)   ? "t4_h8_s8"
+                     : nodes >= ((int64_t)1 << 22) ? "t4_h12_s4"
                      : nodes >= ((int64_t)1 << 21) ? "t3_h8_s8"
                      : nodes >= ((int64_t)1 << 20) ? "t2_h4"
                                                    : "v1_ty1_xcd";
@@ -1324,22 +1351,25 @@ hipError_t launch_step(const StepArgs& a, int v, hipStream_t s) {
 #undef LBM_T2
     return hipErrorInvalidValue;
   }
-  if (var.steps == 3) {
+  if (var.steps >= 3) {
     const int per = (var.tile_y + var.sub - 1) / var.sub;
     const int blocks = (a.n_gen * per + 3) / 4 + (a.t.ntx * a.t.nty + 3) / 4;
     const dim3 grid((unsigned)blocks), block(256);
-#define LBM_T3(NT, H, SUB)                                                 \
-  if (var.nontemporal == NT && var.tile_y == H && var.sub == SUB) {        \
-    hipLaunchKernelGGL((step3_kernel<NT, H, SUB>), grid, block, 0, s, a);  \
-    return hipGetLastError();                                              \
+#define LBM_TN(NT, H, SUB, S)                                                        \
+  if (var.nontemporal == NT && var.tile_y == H && var.sub == SUB && var.steps == S) { \
+    hipLaunchKernelGGL((multistep_kernel<NT, H, SUB, S>), grid, block, 0, s, a);     \
+    return hipGetLastError();                                                        \
   }
-    LBM_T3(false, 4, 4)
-    LBM_T3(false, 6, 4)
-    LBM_T3(false, 8, 4)
-    LBM_T3(false, 12, 4)
-    LBM_T3(false, 16, 4)
-    LBM_T3(false, 8, 8)
-#undef LBM_T3
+    LBM_TN(false, 4, 4, 3)
+    LBM_TN(false, 6, 4, 3)
+    LBM_TN(false, 8, 4, 3)
+    LBM_TN(false, 12, 4, 3)
+    LBM_TN(false, 8, 8, 3)
+    LBM_TN(false, 8, 4, 4)
+    LBM_TN(false, 8, 8, 4)
+    LBM_TN(false, 12, 4, 4)
+    LBM_TN(false, 12, 12, 4)
+#undef LBM_TN
     return hipErrorInvalidValue;
   }
   const dim3 grid((unsigned)(a.t.ntx * a.t.nty)), block(256);

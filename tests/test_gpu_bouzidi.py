@@ -46,10 +46,10 @@ def test_paper_lattice_fields_and_forces():
 
 
 def test_full_size_multi_step_all_nodes():
-    """3280 x 1680 (D = 80, the three-step kernel by default) from a
+    """3280 x 1680 (D = 80, the four-step kernel by default) from a
     disturbed state: every population after one launch."""
     kw = dict(WORKLOADS["cyl_d80"], **INTERP)
-    lat, o, (fx, fy, _, _), (ofx, ofy) = run_both(kw, 3, seed=80, amp=0.02)
+    lat, o, (fx, fy, _, _), (ofx, ofy) = run_both(kw, 4, seed=80, amp=0.02)
     f = lat.get_populations(np.float64)
     of = o.get_fstar()
     solid = oracle.digitise(oracle.OracleParams(**_oracle_kwargs(kw)))

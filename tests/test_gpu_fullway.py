@@ -68,10 +68,10 @@ def test_paper_lattice_fields_and_forces():
 
 
 def test_full_size_multi_step_all_nodes():
-    """3280 x 1680 (D = 80, the three-step kernel by default) from a
+    """3280 x 1680 (D = 80, the four-step kernel by default) from a
     disturbed state: every population of every node after one launch."""
     kw = dict(WORKLOADS["cyl_d80"], **FULL)
-    lat, o, (fx, fy, _, _), (ofx, ofy) = run_both(kw, 3, seed=81, amp=0.02)
+    lat, o, (fx, fy, _, _), (ofx, ofy) = run_both(kw, 4, seed=81, amp=0.02)
     err = np.abs(lat.get_populations(np.float64) - o.get_fstar()).max()
     note(f"  variant {lbm.variant_name(lat.variant)} max |df*| {err:.2e}")
     assert err <= 1e-5

@@ -85,10 +85,11 @@ def test_c1_force_trace_2000_steps():
 @pytest.mark.parametrize("name", ["cyl_d80", "cyl_d160", "slab_d160_of8"])
 def test_full_size_multi_step_all_nodes(name):
     """The benchmark's lattices in the benchmark's launch configuration:
-    three steps from a disturbed state (one launch of the three-step kernel
-    by default on all three lattices), every node against the oracle."""
+    four steps from a disturbed state (one launch of the four-step kernel
+    by default at D = 80 and D = 160, a three-step and a one-step launch on
+    the slab), every node against the oracle."""
     kw = dict(WORKLOADS[name])
-    lat, o, (fx, fy, _, _), (ofx, ofy) = run_both(kw, 3, seed=160, amp=0.02)
+    lat, o, (fx, fy, _, _), (ofx, ofy) = run_both(kw, 4, seed=160, amp=0.02)
     f = lat.get_populations(np.float64)
     of = o.get_fstar()
     solid = oracle.digitise(oracle.OracleParams(**_oracle_kwargs(kw)))
@@ -220,7 +221,7 @@ def test_graph_replay_matches_plain_launches():
 
 
 # ------------------------------------------- two steps per launch
-TWO_STEP = [v for v in range(1, lbm.num_variants() + 1) if lbm.variant_name(v)[:3] in ("t2_", "t3_")]
+TWO_STEP = [v for v in range(1, lbm.num_variants() + 1) if lbm.variant_name(v)[:3] in ("t2_", "t3_", "t4_")]
 
 
 def _two_step_cases():
@@ -262,13 +263,14 @@ def test_two_step_variants_match_one_step_bitwise(case):
 
 def test_default_variant_follows_the_lattice_size():
     """One step per launch below 2^20 nodes (cached stores, XCD bands), two
-    from 2^20, three from 2^21 (boundary waves of 8 rows, of 4 between 2^22
-    and 2^24); variant 0 restores the default."""
+    from 2^20, three from 2^21, four from 2^22 (12-row segments with 4-row
+    boundary pieces below 2^24, 8-row segments and pieces above); variant 0
+    restores the default."""
     small = lbm.Lattice(lbm.make_params(**WORKLOADS["cyl_d10"]))
     big = lbm.Lattice(lbm.make_params(**WORKLOADS["cyl_d40"]))
     assert lbm.variant_name(small.variant) == "v1_ty1_xcd"
     assert lbm.variant_name(big.variant) == "t2_h4"
-    for name, want in (("slab_d160_of8", "t3_h8_s8"), ("cyl_d80", "t3_h8_s4"), ("cyl_d160", "t3_h8_s8")):
+    for name, want in (("slab_d160_of8", "t3_h8_s8"), ("cyl_d80", "t4_h12_s4"), ("cyl_d160", "t4_h8_s8")):
         lat = lbm.Lattice(lbm.make_params(**WORKLOADS[name]))
         assert lbm.variant_name(lat.variant) == want, name
         lat.close()
