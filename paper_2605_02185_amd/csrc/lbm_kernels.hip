@@ -40,13 +40,16 @@ constexpr float W0 = 4.0f / 9.0f, W1 = 1.0f / 9.0f, W2 = 1.0f / 36.0f;
 // Eq. 4 then Eqs. 2-3 on the nine streamed and corrected deviations
 // g_k = f_k - w_k, giving the post-collision deviations out.  With
 // drho = rho - 1 = sum g_k and j = sum c_k g_k:
-//   f_eq,k - w_k = w_k [drho + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)].
-// Flags a density that is non-finite or outside (0, 10).  Contraction is
-// off and every fused multiply-add is written out, so that each kernel
-// variant (scalar or vector bulk path, general path) rounds identically.
+//   f_eq,k - w_k = w_k [drho + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)],
+// and the relaxation g + omega (f_eq - w - g) is formed as
+// (1 - omega) g + (omega w) [drho + rho (...)], one instruction fewer per
+// population (the factors are uniform across the wave).  Contraction is off
+// and every fused multiply-add is written out, so that each kernel variant
+// (scalar or vector bulk path, general path) rounds identically.
 __device__ __forceinline__ void collide_bgk(const float (&g)[9], float drho, float rho, float ux, float uy,
                                             float omega, float (&out)[9]) {
 #pragma clang fp contract(off)
+  const float keep = 1.0f - omega;
   const float usq = 1.5f * __fmaf_rn(ux, ux, uy * uy);
   float cu[9];
   cu[0] = 0.0f;
@@ -60,10 +63,9 @@ __device__ __forceinline__ void collide_bgk(const float (&g)[9], float drho, flo
   cu[8] = ux - uy;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    const float w = k == 0 ? W0 : (k < 5 ? W1 : W2);
+    const float ow = omega * (k == 0 ? W0 : (k < 5 ? W1 : W2));
     const float poly = __fmaf_rn(cu[k], __fmaf_rn(4.5f, cu[k], 3.0f), -usq);
-    const float feq = w * __fmaf_rn(rho, poly, drho);
-    out[k] = __fmaf_rn(omega, feq - g[k], g[k]);
+    out[k] = __fmaf_rn(keep, g[k], ow * __fmaf_rn(rho, poly, drho));
   }
 }
 
@@ -113,11 +115,14 @@ __device__ __forceinline__ void collide_mrt(const float (&g)[9], float drho, flo
   out[8] = g[8] - ((diag - a8) + (a4 - a6));
 }
 
+// Moments (Eq. 4) and the collision.  1/rho is the hardware reciprocal
+// (within 1 ulp): a correctly rounded division costs about ten instructions,
+// a tenth of the whole collision.
 __device__ __forceinline__ void collide(const float (&g)[9], const Physics& p, float (&out)[9], bool& bad) {
 #pragma clang fp contract(off)
   const float drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
   const float rho = 1.0f + drho;
-  const float ir = 1.0f / rho;
+  const float ir = __builtin_amdgcn_rcpf(rho);
   const float jx = ((g[1] - g[3]) + (g[5] - g[7])) + (g[8] - g[6]);
   const float jy = ((g[2] - g[4]) + (g[5] - g[7])) + (g[6] - g[8]);
   const float ux = jx * ir;
