@@ -42,9 +42,10 @@ def kernel_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def stored_traffic(workload: str, collision: str, variant: str):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source, workload, collision and variant."""
+def stored_counters(workload: str, collision: str, variant: str):
+    """The committed counter summary (HBM bytes per launch, and the vector
+    ALU figures when recorded), if it was taken on the current kernel source,
+    workload, collision and variant; else None."""
     try:
         d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
@@ -52,7 +53,7 @@ def stored_traffic(workload: str, collision: str, variant: str):
     if (d.get("kernel_sha256_16") != kernel_hash() or d.get("workload") != workload
             or d.get("collision", "bgk") != collision or d.get("variant") != variant):
         return None
-    return d.get("bytes_per_launch")
+    return d
 
 
 def copy_ceiling(torch, lbm, nbytes: int, reps: int = 20) -> float:
@@ -163,7 +164,9 @@ def main():
     steps_per_launch = {"t2": 2, "t3": 3, "t4": 4}.get(vname[:2], 1)
     launch_ms = ms_per_step * steps_per_launch
     achieved = BYTES_PER_NODE * nodes * steps_per_launch / (launch_ms * 1e-3) / 1e9
-    traffic = stored_traffic(args.workload, args.collision, vname)
+    counters = stored_counters(args.workload, args.collision, vname)
+    traffic = counters.get("bytes_per_launch") if counters else None
+    valu = counters.get("valu") if counters else None
     roof = {
         "bound": "hbm",
         "achieved": round(achieved, 1),
@@ -177,6 +180,10 @@ def main():
         "algorithmic_bytes_per_launch": BYTES_PER_NODE * nodes * steps_per_launch,
         "hbm_GBs": round(traffic / (launch_ms * 1e-3) / 1e9, 1) if traffic else None,
     }
+    if valu:
+        # the vector ALU side of the same kernel, from the stored counters
+        roof["valu_busy_pct"] = valu["valu_busy_pct"]
+        roof["fp32_TFLOPs"] = round(valu["fp32_flop_per_launch"] / (launch_ms * 1e-3) / 1e12, 2)
     out = {
         "metric": "D2Q9 MLUPS & % HBM roofline",
         "value": round(mlups, 1),

@@ -7,8 +7,15 @@ known size, run in the same process: FETCH_SIZE and WRITE_SIZE count in
 units that differ from bytes by a fixed factor on this chip.
 
     python bench_traffic.py FETCH_CSV WRITE_CSV --variant t2_h4 [--workload cyl_d160] [--collision bgk]
+                            [--valu VALU_CSV]
 
 The variant is the one bench.py reports in config.variant for the same run.
+With --valu, a third run's counters (SQ_INSTS_VALU, SQ_INSTS_VALU_FMA_F32,
+SQ_INSTS_VALU_ADD_F32, SQ_INSTS_VALU_MUL_F32, SQ_INSTS_VALU_TRANS_F32,
+SQ_ACTIVE_INST_VALU, GRBM_GUI_ACTIVE) add the vector-ALU side: FP32
+operations per launch (64 lanes per wave instruction, two per FMA) and the
+VALU busy percentage, 100 SQ_ACTIVE_INST_VALU / CUs / (GRBM_GUI_ACTIVE /
+XCDs), the GRBM count being the sum over the XCDs.
 """
 import argparse
 import csv
@@ -35,6 +42,7 @@ def main():
     ap.add_argument("--workload", default="cyl_d160")
     ap.add_argument("--collision", default="bgk")
     ap.add_argument("--variant", required=True)
+    ap.add_argument("--valu", help="counter_collection.csv of the VALU counter run")
     a = ap.parse_args()
     steps = {"t2": 2, "t3": 3, "t4": 4}.get(a.variant[:2], 1)
     kname = {1: "step_kernel<", 2: "step2_kernel"}.get(steps, "multistep_kernel")
@@ -77,6 +85,23 @@ def main():
         "fetch_scale": round(fetch_scale, 5),
         "write_scale": round(write_scale, 5),
     }
+    if a.valu:
+        c = {n: per_dispatch(a.valu, n, kname)[0] for n in (
+            "SQ_INSTS_VALU", "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32",
+            "SQ_INSTS_VALU_TRANS_F32", "SQ_ACTIVE_INST_VALU", "GRBM_GUI_ACTIVE")}
+        agent = [r for r in csv.DictReader(open(os.path.join(os.path.dirname(a.valu), "run_agent_info.csv")))
+                 if r["Agent_Type"] == "GPU"][0]
+        cus, xcc = int(agent["Cu_Count"]), int(agent["Num_Xcc"])
+        flop = 64 * (2 * c["SQ_INSTS_VALU_FMA_F32"] + c["SQ_INSTS_VALU_ADD_F32"] + c["SQ_INSTS_VALU_MUL_F32"]
+                     + c["SQ_INSTS_VALU_TRANS_F32"])
+        out["valu"] = {
+            "counters_per_launch": {k: round(v) for k, v in c.items()},
+            "cus": cus, "xcc": xcc,
+            "fp32_flop_per_launch": round(flop),
+            "fp32_flop_per_update": round(flop / (nodes * steps), 1),
+            "valu_insts_per_update": round(64 * c["SQ_INSTS_VALU"] / (nodes * steps), 1),
+            "valu_busy_pct": round(100 * c["SQ_ACTIVE_INST_VALU"] / cus / (c["GRBM_GUI_ACTIVE"] / xcc), 1),
+        }
     with open(bench.TRAFFIC_FILE, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
