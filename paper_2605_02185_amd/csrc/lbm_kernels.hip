@@ -117,8 +117,11 @@ __device__ __forceinline__ void collide_mrt(const float (&g)[9], float drho, flo
 
 // Moments (Eq. 4) and the collision.  1/rho is the hardware reciprocal
 // (within 1 ulp): a correctly rounded division costs about ten instructions,
-// a tenth of the whole collision.
-__device__ __forceinline__ void collide(const float (&g)[9], const Physics& p, float (&out)[9], bool& bad) {
+// a tenth of the whole collision.  COLL picks the operator at compile time
+// (kBgk, kMrt) or from p.mrt (kEither); the arithmetic is the same either way.
+enum : int { kBgk = 0, kMrt = 1, kEither = 2 };
+template <int COLL>
+__device__ __forceinline__ void collide_t(const float (&g)[9], const Physics& p, float (&out)[9], bool& bad) {
 #pragma clang fp contract(off)
   const float drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
   const float rho = 1.0f + drho;
@@ -128,10 +131,14 @@ __device__ __forceinline__ void collide(const float (&g)[9], const Physics& p, f
   const float ux = jx * ir;
   const float uy = jy * ir;
   bad |= !(rho > 0.0f && rho < 10.0f);
-  if (p.mrt)
+  if (COLL == kMrt || (COLL == kEither && p.mrt))
     collide_mrt(g, drho, rho, ux, uy, jx, jy, p, out);
   else
     collide_bgk(g, drho, rho, ux, uy, p.omega, out);
+}
+
+__device__ __forceinline__ void collide(const float (&g)[9], const Physics& p, float (&out)[9], bool& bad) {
+  collide_t<kEither>(g, p, out, bad);
 }
 
 template <bool NT>
@@ -373,6 +380,7 @@ __device__ __forceinline__ void gather(const StepArgs& a, int x, int y, uint16_t
 // fluid: pull, boundary corrections, force contributions (written when
 // `owner`), collision.  Solid nodes keep their (never streamed) values, or
 // with full-way bounce-back pull theirs and send them back reversed.
+template <int COLL = kEither>
 __device__ __forceinline__ void general_update(const StepArgs& a, int x, int y, bool owner, float (&out)[9],
                                                bool& bad) {
   const int nx = a.g.nx, ny = a.g.ny;
@@ -419,7 +427,7 @@ __device__ __forceinline__ void general_update(const StepArgs& a, int x, int y, 
     }
     link_force(a.g, a.partial, x, y, fl, g, own, a.p);
   }
-  collide(g, a.p, out, bad);
+  collide_t<COLL>(g, a.p, out, bad);
 }
 
 template <bool NT>
@@ -646,15 +654,16 @@ __device__ __forceinline__ void prefetch_bulk(const StepArgs& a, int x, int y, f
 
 // f*(t+1) at (x, y) for one lane; `active` false gives zeros (outside the
 // lattice), `owner` selects who records forces and density failures.
+template <int COLL = kEither>
 __device__ __forceinline__ void first_update(const StepArgs& a, int x, int y, bool active, bool owner,
                                              const float (&pre)[9], float (&out)[9], bool& bad) {
   const int nx = a.g.nx, ny = a.g.ny;
   const bool special = active && (x == 0 || x >= nx - 1 || y == 0 || y == ny - 1 || in_rect(a.g, x, y));
   bool b = false;
   if (__any(special)) {
-    if (active) general_update(a, x, y, owner, out, b);
+    if (active) general_update<COLL>(a, x, y, owner, out, b);
   } else if (active) {
-    collide(pre, a.p, out, b);  // the bulk pull, loaded ahead
+    collide_t<COLL>(pre, a.p, out, b);  // the bulk pull, loaded ahead
   }
   if (!active) {
 #pragma unroll
@@ -668,6 +677,7 @@ __device__ __forceinline__ void first_update(const StepArgs& a, int x, int y, bo
 // from f*(t+2)).  The same steps as general_update, with the pulled values
 // taken from registers; link forces go to `partial`.  Inactive lanes leave
 // `out` unset (nothing reads it: their node is outside the lattice).
+template <int COLL = kEither>
 __device__ __forceinline__ void second_update(const StepArgs& a, double2* __restrict__ partial, int x, int y,
                                               bool active, bool owner, const float (&w0)[9],
                                               const float (&w1)[9], const float (&w2)[9], float (&out)[9],
@@ -687,7 +697,7 @@ __device__ __forceinline__ void second_update(const StepArgs& a, double2* __rest
   const bool special = active && (x == 0 || x >= nx - 1 || y == 0 || y == ny - 1 || in_rect(a.g, x, y));
   bool b = false;
   if (!__any(special)) {
-    if (active) collide(c, a.p, out, b);
+    if (active) collide_t<COLL>(c, a.p, out, b);
     bad |= b && owner;
     return;
   }
@@ -758,7 +768,7 @@ __device__ __forceinline__ void second_update(const StepArgs& a, double2* __rest
   }
   if (open_x && x == 0) inlet_bc(a.p, corner_y, g);
   if ((fl >> 1) && owner) link_force(a.g, partial, x, y, fl, g, w1, a.p);
-  collide(g, a.p, out, b);
+  collide_t<COLL>(g, a.p, out, b);
   bad |= b && owner;
 }
 
@@ -939,8 +949,10 @@ __device__ __forceinline__ double2* level_partial(const StepArgs& a, int l) {
 // y0 - h + i from memory and level l on row y0 - h + i - (l - 1) from the
 // rows of level l - 1 made in iterations i - 2 .. i; loads run AHEAD rows
 // ahead of level 1 (all of them first when they fit), outputs are stored at
-// the end.
-template <bool NT, int H, int S>
+// the end.  The collision operator is fixed at compile time (COLL): the
+// kernel's code then holds one operator's bulk path only, which keeps it
+// within the instruction cache better.
+template <bool NT, int H, int S, int COLL>
 __device__ __forceinline__ void bulk_wave_n(const StepArgs& a, int strip, int seg) {
   constexpr int h = S - 1, W = 64 - 2 * h;
   const int lane = (int)(threadIdx.x & 63);
@@ -961,7 +973,7 @@ __device__ __forceinline__ void bulk_wave_n(const StepArgs& a, int strip, int se
   for (int i = 0; i < N1; ++i) {
     if (i + AHEAD < N1) load_pull(a, x, y0 - h + i + AHEAD, pre[(i + AHEAD) % R]);
     bool b1 = false;
-    collide(pre[i % R], a.p, w[0][i % 3], b1);
+    collide_t<COLL>(pre[i % R], a.p, w[0][i % 3], b1);
     if (i >= h && i < h + H) bad[0] |= b1;
 #pragma unroll
     for (int l = 2; l <= S; ++l) {
@@ -970,11 +982,11 @@ __device__ __forceinline__ void bulk_wave_n(const StepArgs& a, int strip, int se
       pull_rows(w[l - 2][(i + 1) % 3], w[l - 2][(i + 2) % 3], w[l - 2][i % 3], c);
       if (l < S) {
         bool b = false;
-        collide(c, a.p, w[l - 1][i % 3], b);
+        collide_t<COLL>(c, a.p, w[l - 1][i % 3], b);
         const int q = i - h - (l - 1);  // row - y0
         if (q >= 0 && q < H) bad[l - 1] |= b;
       } else {
-        collide(c, a.p, out[i - 2 * h], bad[S - 1]);
+        collide_t<COLL>(c, a.p, out[i - 2 * h], bad[S - 1]);
       }
     }
   }
@@ -990,7 +1002,7 @@ __device__ __forceinline__ void bulk_wave_n(const StepArgs& a, int strip, int se
 // is not interior, with the boundary code on every level; a rolled loop like
 // general_wave's over the first-level rows r, each level l > 1 following on
 // row r - (l - 1).
-template <bool NT, int SUB, int S>
+template <bool NT, int SUB, int S, int COLL>
 __device__ __forceinline__ void general_wave_n(const StepArgs& a, int segment, int sub) {
   constexpr int h = S - 1, W = 64 - 2 * h;
   const int lane = (int)(threadIdx.x & 63);
@@ -1031,7 +1043,7 @@ __device__ __forceinline__ void general_wave_n(const StepArgs& a, int segment, i
       lv[0][1][k] = lv[0][2][k];
     }
     // level 1 (f*(t+1)) of row r
-    first_update(a, x, row_of(r), col_ok && row_ok(r), out_col && r >= y0 && r < y1, pre, lv[0][2], bad[0]);
+    first_update<COLL>(a, x, row_of(r), col_ok && row_ok(r), out_col && r >= y0 && r < y1, pre, lv[0][2], bad[0]);
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       pre[k] = pre1[k];
@@ -1047,11 +1059,11 @@ __device__ __forceinline__ void general_wave_n(const StepArgs& a, int segment, i
           lv[l - 1][0][k] = lv[l - 1][1][k];
           lv[l - 1][1][k] = lv[l - 1][2][k];
         }
-        second_update(a, level_partial(a, l), x, row_of(q), col_ok && row_ok(q), out_col && q >= y0 && q < y1,
+        second_update<COLL>(a, level_partial(a, l), x, row_of(q), col_ok && row_ok(q), out_col && q >= y0 && q < y1,
                       lv[l - 2][0], lv[l - 2][1], lv[l - 2][2], lv[l - 1][2], bad[l - 1]);
       } else {
         float out[9];
-        second_update(a, level_partial(a, l), x, q, col_ok, out_col, lv[l - 2][0], lv[l - 2][1], lv[l - 2][2], out,
+        second_update<COLL>(a, level_partial(a, l), x, q, col_ok, out_col, lv[l - 2][0], lv[l - 2][1], lv[l - 2][2], out,
                       bad[S - 1]);
         if (out_col) store9<NT>(a.B, P, (uint32_t)q * Wp + (uint32_t)x, out);
       }
@@ -1062,18 +1074,18 @@ __device__ __forceinline__ void general_wave_n(const StepArgs& a, int segment, i
 }
 
 // One launch, S steps; blocks as in step2_kernel.
-template <bool NT, int H, int SUB, int S>
+template <bool NT, int H, int SUB, int S, int COLL>
 __global__ __launch_bounds__(256) void multistep_kernel(StepArgs a) {
   constexpr int per = (H + SUB - 1) / SUB;
   const int gen_blocks = (a.n_gen * per + 3) / 4;
   const int b = (int)blockIdx.x, w = (int)(threadIdx.x >> 6);
   if (b < gen_blocks) {
     const int wave = b * 4 + w;
-    if (wave < a.n_gen * per) general_wave_n<NT, SUB, S>(a, a.gen[wave / per], wave % per);
+    if (wave < a.n_gen * per) general_wave_n<NT, SUB, S, COLL>(a, a.gen[wave / per], wave % per);
     return;
   }
   const int wave = (b - gen_blocks) * 4 + w;
-  if (wave < a.t.ntx * a.t.nty) bulk_wave_n<NT, H, S>(a, wave % a.t.ntx, wave / a.t.ntx);
+  if (wave < a.t.ntx * a.t.nty) bulk_wave_n<NT, H, S, COLL>(a, wave % a.t.ntx, wave / a.t.ntx);
 }
 
 // One step of a whole ensemble: block b processes tile tiles[b] = (case,
@@ -1360,10 +1372,13 @@ hipError_t launch_step(const StepArgs& a, int v, hipStream_t s) {
     const int per = (var.tile_y + var.sub - 1) / var.sub;
     const int blocks = (a.n_gen * per + 3) / 4 + (a.t.ntx * a.t.nty + 3) / 4;
     const dim3 grid((unsigned)blocks), block(256);
-#define LBM_TN(NT, H, SUB, S)                                                        \
-  if (var.nontemporal == NT && var.tile_y == H && var.sub == SUB && var.steps == S) { \
-    hipLaunchKernelGGL((multistep_kernel<NT, H, SUB, S>), grid, block, 0, s, a);     \
-    return hipGetLastError();                                                        \
+#define LBM_TN(NT, H, SUB, S)                                                            \
+  if (var.nontemporal == NT && var.tile_y == H && var.sub == SUB && var.steps == S) {     \
+    if (a.p.mrt)                                                                          \
+      hipLaunchKernelGGL((multistep_kernel<NT, H, SUB, S, kMrt>), grid, block, 0, s, a);  \
+    else                                                                                  \
+      hipLaunchKernelGGL((multistep_kernel<NT, H, SUB, S, kBgk>), grid, block, 0, s, a);  \
+    return hipGetLastError();                                                            \
   }
     LBM_TN(false, 4, 4, 3)
     LBM_TN(false, 6, 4, 3)
