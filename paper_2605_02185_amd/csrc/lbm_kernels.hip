@@ -10,6 +10,7 @@
 // buffer A = f*(t) into buffer B = f*(t+1) node by node:
 //   1. pull: f_k(x) = f*_k(x - c_k)                               (Eq. 2, LHS)
 //      half-way bounce-back where x - c_k is solid: f_k(x) = f*_opp(k)(x)
+//      (or interpolated bounce-back, Sec. 2.4, or full-way, Sec. 3.1)
 //   2. boundary corrections of the populations missing at the edges
 //      (Sec. 2.3: free-slip Eq. 7, periodic Eq. 8, NEBB Eqs. 9-10, moving-wall
 //      bounce-back Eq. 11; outlet Eq. 13; Zou-He velocity inlet, Sec. 3.1)
@@ -23,6 +24,13 @@
 // Waves whose 64 nodes are all interior fluid nodes away from the cylinder
 // take a branch-free bulk path; any other wave takes the general path, which
 // looks the cylinder's bounce-back links up in a small flag rectangle.
+//
+// step2_kernel and multistep_kernel take the same per-node steps two, three
+// or four times in one launch (temporal blocking): each wave keeps the
+// intermediate levels f*(t+1) .. f*(t+S-1) of a strip of columns in
+// registers, reaching x-neighbours by DPP lane shifts, recomputes one more
+// column and row on every side per level, and stores only f*(t+S).  Every
+// variant gives the same bits as one step per launch.
 #include "lbm_internal.h"
 
 #include <climits>
