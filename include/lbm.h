@@ -196,8 +196,8 @@ lbm_status lbm_shedding_stats(const double* cd, const double* cl, int64_t n, dou
  * updates; the steps left over (a remainder of n, or the steps of a learned
  * closure, which "t3_*" and "t4_*" variants run one at a time) run the
  * one-step kernel.  The default of
- * a new context is "t4_h8_s8" from 2^24 nodes, "t4_h12_s4" from 2^22,
- * "t3_h8_s8" from 2^21, "t2_h4" from 2^20 and the one-step "v1_ty1_xcd"
+ * a new context is "t4_h8_s8" from 2^24 nodes, "t4_h8_s4" from 2^22,
+ * "t3_h8_s4" from 2^21, "t4_h8_s2" from 2^20 and the one-step "v1_ty1_xcd"
  * (cached stores, each XCD on its own band of rows) below ("_sN": segments
  * that need the boundary code run in pieces of N rows).  lbm_get_variant
  * reports the variant in use. */

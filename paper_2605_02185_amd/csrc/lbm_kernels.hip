@@ -1297,6 +1297,8 @@ constexpr Variant kVariants[] = {
     {"t4_h8_s8", kStrip4, 8, 1, 0, 0, 4, 8},
     {"t4_h12_s4", kStrip4, 12, 1, 0, 0, 4, 4},
     {"t4_h12_s12", kStrip4, 12, 1, 0, 0, 4, 12},
+    {"t3_h8_s2", kStrip3, 8, 1, 0, 0, 3, 2},
+    {"t4_h8_s2", kStrip4, 8, 1, 0, 0, 4, 2},
 };
 
 }  // namespace
@@ -1304,23 +1306,21 @@ constexpr Variant kVariants[] = {
 int num_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 const Variant& variant(int v) { return kVariants[v - 1]; }
 
-// The two-step kernel pays once its interior segments fill the chip (1.3x at
-// 5.5 M nodes, even at 1.4 M, slower below).  Smaller lattices live in the
-// caches: there the one-step kernel with cached stores and each XCD on its
-// own band of rows is fastest (10-25 % over the plain order at 86 k-800 k
-// nodes; the plain order wins once the lattice streams from HBM).  Boundary
-// waves of 4 rows gain 2-17 % from 2.8 M nodes on and lose 25 % at 1.4 M,
-// where the launch lasts about as long as one such wave.  Three steps per
-// launch gain 29 % at 5.5 M nodes and 45 % at 22 M, 5 % at 2.8 M (an
-// x-periodic slab), and lose 20 % at 1.4 M; four steps gain another 16 % at
-// 22 M and 6 % at 5.5 M but lose 5 % on the slab.  Boundary waves take 8
-// rows where the launch is long (22 M nodes) or the boundary strips are
-// many (the slab: 2 of 14), 4 rows in between (5.5 M).
+// Measured on the MI355X (BGK, D2Q9 cylinder channels and one x-periodic
+// slab): below 2^20 nodes the lattice lives in the caches and one launch per
+// step, with cached stores and each XCD on its own band of rows, is fastest
+// (the deeper kernels' boundary waves set their launch time there).  From
+// 2^20 nodes fused steps win: at 1.4 M nodes four steps with 2-row boundary
+// pieces (98 k MLUPS against 88 k for two steps), at 2.8 M three steps with
+// 4-row pieces (147 k), at 5.5 M four steps with 4-row pieces (173 k), at
+// 22 M four steps with 8-row pieces (204 k; one step per launch: 82 k).
+// Longer boundary pieces recompute fewer rows but lengthen the serial chain
+// of each boundary wave, which only the longest launches hide.
 int default_variant(int64_t nodes) {
   const char* want = nodes >= ((int64_t)1 << 24)   ? "t4_h8_s8"
-                     : nodes >= ((int64_t)1 << 22) ? "t4_h12_s4"
-                     : nodes >= ((int64_t)1 << 21) ? "t3_h8_s8"
-                     : nodes >= ((int64_t)1 << 20) ? "t2_h4"
+                     : nodes >= ((int64_t)1 << 22) ? "t4_h8_s4"
+                     : nodes >= ((int64_t)1 << 21) ? "t3_h8_s4"
+                     : nodes >= ((int64_t)1 << 20) ? "t4_h8_s2"
                                                    : "v1_ty1_xcd";
   for (int v = 1; v <= num_variants(); ++v)
     if (std::strcmp(kVariants[v - 1].name, want) == 0) return v;
@@ -1397,6 +1397,8 @@ hipError_t launch_step(const StepArgs& a, int v, hipStream_t s) {
     LBM_TN(false, 8, 8, 4)
     LBM_TN(false, 12, 4, 4)
     LBM_TN(false, 12, 12, 4)
+    LBM_TN(false, 8, 2, 3)
+    LBM_TN(false, 8, 2, 4)
 #undef LBM_TN
     return hipErrorInvalidValue;
   }
