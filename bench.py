@@ -224,14 +224,15 @@ def main():
 
 def ensemble_result(torch, lbm, steps: int = 1280) -> dict:
     """The 64 cylinder channels (D 8..32, Re 60..200, U = 0.05, tau from Re,
-    MRT with the rates of Sec. 2.1): one Ensemble against the same cases as
-    64 separate lattices stepped one after the other, both after 128 warm-up
-    steps; MLUPS over all nodes of all cases."""
+    MRT with the rates of Sec. 2.1): one Ensemble (its default variant)
+    against the same cases as 64 separate lattices stepped one after the
+    other, both after 128 warm-up steps; MLUPS over all nodes of all cases."""
     from lbm_inputs import ensemble
 
     cases = ensemble(mrt=True)
     nodes = sum(c["nx"] * c["ny"] for c in cases)
     ens = lbm.Ensemble([lbm.make_params(**c) for c in cases])
+    vname = lbm.variant_name(ens.variant)
     ens.step(128)
     ens.sync()
     t0 = time.perf_counter()
@@ -251,7 +252,7 @@ def ensemble_result(torch, lbm, steps: int = 1280) -> dict:
     t_sep = time.perf_counter() - t0
     for lat in lats:
         lat.close()
-    return {"cases": len(cases), "nodes": nodes, "steps": steps,
+    return {"cases": len(cases), "nodes": nodes, "steps": steps, "variant": vname,
             "mlups": round(nodes * steps / t_ens / 1e6, 1),
             "separate_mlups": round(nodes * steps / t_sep / 1e6, 1),
             "speedup": round(t_sep / t_ens, 3)}

@@ -228,16 +228,19 @@ lbm_status lbm_autotune(lbm_ctx* ctx, int32_t steps, const char* cache_path, int
 
 /* ------------------------------------------------------------------ ensemble
  * An ensemble advances many independent lattices (e.g. cylinder channels of
- * different D, Re and size) together: every step is one kernel launch over a
- * flattened list of the tiles of all active cases, and 96-step chunks are
- * replayed as HIP graphs.  Each case evolves bit for bit as it would in its
- * own context.  Cases are identified by their index in the `cases` array. */
+ * different D, Re and size) together: every launch (of one step, or of three
+ * or four with a multi-step variant) covers a flattened list of the tiles or
+ * wave tasks of all active cases, and 96-step chunks are replayed as HIP
+ * graphs.  Each case evolves bit for bit as it would in its own context.
+ * Cases are identified by their index in the `cases` array. */
 typedef struct lbm_batch lbm_batch;
 
 /* `cases[n]` as for lbm_create; `budgets` (may be NULL = unlimited) gives the
  * number of steps after which each case stops (retires) while the others go
  * on.  `tune_cache` (may be NULL) enables the autotuner with that cache file;
- * without it the default kernel variant is used. */
+ * without it the default kernel variant is used: "t4_h8_s8" (four steps per
+ * launch) when the cases hold 2^22 nodes or more together, else the one-step
+ * "v1_ty1_nt". */
 lbm_status lbm_batch_create(const lbm_params* cases, const int64_t* budgets, int32_t n, void* stream,
                             const char* tune_cache, lbm_batch** out);
 void lbm_batch_destroy(lbm_batch* b);
@@ -261,6 +264,16 @@ lbm_status lbm_batch_get_populations(lbm_batch* b, int32_t c, void* buf, int dty
 
 /* Kernel variant in use (1-based, as lbm_variant_name). */
 int32_t lbm_batch_variant(const lbm_batch* b);
+
+/* Select the ensemble's kernel variant (synchronises the ensemble's stream;
+ * also done by the autotuner).  Allowed: the one-step variants without a
+ * remapped block order, and the multi-step variants "t3_h8_s2", "t3_h8_s4",
+ * "t4_h8_s2", "t4_h8_s4" and "t4_h8_s8", which advance every active case by
+ * their 3 or 4 steps per launch (the steps a case has left before the active
+ * set changes, when fewer, run one per launch on "v1_ty1_nt").  Every
+ * variant gives each case the same bits as running it alone.  Returns
+ * LBM_ERR_INVALID_ARG for any other variant. */
+lbm_status lbm_batch_set_variant(lbm_batch* b, int32_t variant);
 
 /* ------------------------------------------------------ learned closure
  * A small network (36 -> 64 -> 64 -> 3, exact-erf GELU after both hidden

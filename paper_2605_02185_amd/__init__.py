@@ -267,6 +267,9 @@ class Ensemble:
     def variant(self) -> int:
         return _lib.lib.lbm_batch_variant(self._h)
 
+    def set_variant(self, v: int):
+        check(_lib.lib.lbm_batch_set_variant(self._h, v))
+
     def step(self, n: int = 1):
         check(_lib.lib.lbm_batch_step(self._h, n))
 

@@ -112,6 +112,7 @@ def _load():
         "lbm_batch_fields": (i32, [vp, i32, vp, vp, vp, ctypes.c_int]),
         "lbm_batch_get_populations": (i32, [vp, i32, vp, ctypes.c_int, ctypes.c_int]),
         "lbm_batch_variant": (i32, [vp]),
+        "lbm_batch_set_variant": (i32, [vp, i32]),
         "lbm_mlp_create": (i32, [vp, vp, ctypes.POINTER(vp)]),
         "lbm_mlp_destroy": (None, [vp]),
         "lbm_mlp_get_params": (i32, [vp, vp]),

@@ -1,5 +1,6 @@
 // Ensemble runtime of liblbm.so: many independent lattices advanced by one
-// kernel launch per step over the flattened tiles of every active case.
+// kernel launch per step (or per two to four steps with a multi-step
+// variant) over the flattened tiles or wave tasks of every active case.
 #include <algorithm>
 #include <climits>
 #include <cstdio>
@@ -37,14 +38,29 @@ struct lbm_batch {
   std::vector<void*> allocs;         // every device allocation
   int2* d_tiles = nullptr;
   std::vector<int> tile_prefix;      // tiles of the first k cases
+  // multi-step variants: boundary and interior wave tasks of the first k
+  // cases (prefix counts) in two device lists; the steps left over run the
+  // one-step kernel of variant `single`
+  int steps = 1;
+  int single = 1;
+  int2* d_gen_tasks = nullptr;
+  int2* d_bulk_tasks = nullptr;
+  size_t task_cap = 0;
+  std::vector<int> gen_prefix, bulk_prefix;
   int partial_stride = 0;
   int variant = 1;
   int cur = 0;
+  // buffer holding each case's state (budget order): cur while the case is
+  // active, then the buffer of its last launch (a launch flips the buffers
+  // once whatever its number of steps, so this is not the step parity)
+  std::vector<int> case_cur;
   int64_t step = 0;                  // global step counter
   int pending = 0;                   // ring slots used since the last fold
   int pending_active = 0;            // active cases during the pending slots
   hipStream_t capture_stream = nullptr;
-  std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // (cur, active) -> graph
+  // (cur, active) -> graph of kRing steps and whether it leaves the state in
+  // the other buffer (an odd number of launches)
+  std::map<std::pair<int, int>, std::pair<hipGraphExec_t, int>> graphs;
 };
 
 namespace {
@@ -69,38 +85,91 @@ lbm_status fold(lbm_batch* b, hipStream_t s) {
   return LBM_OK;
 }
 
-// One step of the `active` leading cases on stream s.
-lbm_status enqueue(lbm_batch* b, int active, hipStream_t s) {
+// Steps of the next launch with `left` steps to go before the active set
+// changes: the variant's steps when they fit into the force ring, else one.
+int group(const lbm_batch* b, int64_t left) {
+  return b->steps > 1 && left >= b->steps && b->pending + b->steps <= lbm::kRing ? b->steps : 1;
+}
+
+// k steps (1, or the variant's steps as group() allows) of the `active`
+// leading cases on stream s; one launch either way.
+lbm_status enqueue(lbm_batch* b, int active, hipStream_t s, int k = 1) {
   if (b->pending > 0 && active != b->pending_active) {
     lbm_status st = fold(b, s);
     if (st != LBM_OK) return st;
   }
   b->pending_active = active;
-  if (active > 0)
-    BTRY(lbm::launch_step_batch(b->d_cases, b->d_tiles, b->tile_prefix[active], b->cur, b->pending,
-                                b->partial_stride, b->variant, s));
+  if (active > 0) {
+    if (k == 1)
+      BTRY(lbm::launch_step_batch(b->d_cases, b->d_tiles, b->tile_prefix[active], b->cur, b->pending,
+                                  b->partial_stride, b->single, s));
+    else
+      BTRY(lbm::launch_multistep_batch(b->d_cases, b->d_gen_tasks, b->gen_prefix[active], b->d_bulk_tasks,
+                                       b->bulk_prefix[active], b->cur, b->pending, b->partial_stride,
+                                       b->variant, s));
+  }
   b->cur ^= 1;
-  b->step += 1;
-  if (++b->pending == lbm::kRing) return fold(b, s);
+  for (int c = 0; c < active; ++c) b->case_cur[c] = b->cur;
+  b->step += k;
+  b->pending += k;
+  if (b->pending == lbm::kRing) return fold(b, s);
   return LBM_OK;
 }
 
 lbm_status set_variant(lbm_batch* b, int v) {
   b->variant = v;
-  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->steps = lbm::multistep_batch_supported(v) ? lbm::variant(v).steps : 1;
+  b->single = b->steps > 1 ? 1 : v;
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second.first);
   b->graphs.clear();
-  std::vector<int2> tiles;
+  std::vector<int2> tiles, gen, bulk;
   b->tile_prefix.assign(1, 0);
+  b->gen_prefix.assign(1, 0);
+  b->bulk_prefix.assign(1, 0);
   for (int i = 0; i < b->n; ++i) {
-    lbm::tiling_for_variant(b->hcase[i].g, v, &b->hcase[i].t);
-    const int nt = b->hcase[i].t.ntx * b->hcase[i].t.nty;
+    lbm::CaseArgs& c = b->hcase[i];
+    lbm::tiling_for_variant(c.g, b->single, &c.t);
+    const int nt = c.t.ntx * c.t.nty;
     for (int t = 0; t < nt; ++t) tiles.push_back(make_int2(i, t));
     b->tile_prefix.push_back((int)tiles.size());
+    if (b->steps > 1) {
+      lbm::tiling_for_variant(c.g, v, &c.tm);
+      const lbm::Variant& var = lbm::variant(v);
+      const int per = (var.tile_y + var.sub - 1) / var.sub;
+      const bool xper = b->params[i].x_periodic != 0;
+      for (int seg = 0; seg < c.tm.nty; ++seg)
+        for (int strip = 0; strip < c.tm.ntx; ++strip) {
+          const int id = seg * c.tm.ntx + strip;
+          if (lbm::interior_segment(c.g, c.tm, xper, strip, seg))
+            bulk.push_back(make_int2(i, id));
+          else
+            for (int piece = 0; piece < per; ++piece) gen.push_back(make_int2(i, id * per + piece));
+        }
+    } else {
+      c.tm = c.t;
+    }
+    b->gen_prefix.push_back((int)gen.size());
+    b->bulk_prefix.push_back((int)bulk.size());
+  }
+  if (b->steps > 1 && std::max(gen.size(), bulk.size()) > b->task_cap) {
+    // allocations stay until the ensemble is destroyed; grow only
+    const size_t cap = std::max(gen.size(), bulk.size());
+    lbm_status st = dmalloc(b, (void**)&b->d_gen_tasks, sizeof(int2) * std::max<size_t>(cap, 1));
+    if (st != LBM_OK) return st;
+    if ((st = dmalloc(b, (void**)&b->d_bulk_tasks, sizeof(int2) * std::max<size_t>(cap, 1))) != LBM_OK) return st;
+    b->task_cap = cap;
   }
   BTRY(hipMemcpyAsync(b->d_cases, b->hcase.data(), sizeof(lbm::CaseArgs) * b->n, hipMemcpyHostToDevice,
                       b->stream));
   if (b->d_tiles) BTRY(hipMemcpyAsync(b->d_tiles, tiles.data(), sizeof(int2) * tiles.size(),
                                       hipMemcpyHostToDevice, b->stream));
+  if (b->steps > 1) {
+    if (!gen.empty())
+      BTRY(hipMemcpyAsync(b->d_gen_tasks, gen.data(), sizeof(int2) * gen.size(), hipMemcpyHostToDevice, b->stream));
+    if (!bulk.empty())
+      BTRY(hipMemcpyAsync(b->d_bulk_tasks, bulk.data(), sizeof(int2) * bulk.size(), hipMemcpyHostToDevice,
+                          b->stream));
+  }
   BTRY(hipStreamSynchronize(b->stream));
   return LBM_OK;
 }
@@ -121,11 +190,13 @@ std::string tune_key(const lbm_batch* b) {
   return out;
 }
 
-// The ensemble launch walks its flattened tile list in order, one step per
-// launch: variants with a remapped tile order or two steps per launch are
-// for single lattices only.
+// The one-step ensemble launch walks its flattened tile list in order:
+// variants with a remapped tile order are for single lattices only, and of
+// the multi-step variants those with an ensemble kernel.
 bool batch_capable(int v) {
-  return v >= 1 && v <= lbm::num_variants() && !lbm::variant(v).remap_xcd && lbm::variant(v).steps == 1;
+  if (v < 1 || v > lbm::num_variants()) return false;
+  const lbm::Variant& var = lbm::variant(v);
+  return (var.steps == 1 && !var.remap_xcd) || lbm::multistep_batch_supported(v);
 }
 
 int cache_lookup(const char* path, const std::string& key) {
@@ -151,10 +222,24 @@ void cache_store(const char* path, const std::string& key, int v) {
 void free_batch(lbm_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
-  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second.first);
   if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
   for (void* p : b->allocs) (void)hipFree(p);
   delete b;
+}
+
+// Four steps per launch with 8-row boundary pieces once the ensemble holds
+// 2^22 nodes: on the 64 cylinder channels of 55 k - 882 k nodes (26.3 M
+// together, MRT) 117 k MLUPS against 82 k for one step per launch and
+// 103-106 k for the other multi-step variants.  Smaller ensembles keep one
+// step per launch, like the single lattices of their size.
+int batch_default_variant(const lbm_batch* b) {
+  int64_t nodes = 0;
+  for (const auto& p : b->params) nodes += (int64_t)p.nx * p.ny;
+  if (nodes < ((int64_t)1 << 22)) return 1;
+  for (int v = 1; v <= lbm::num_variants(); ++v)
+    if (std::strcmp(lbm::variant(v).name, "t4_h8_s8") == 0 && lbm::multistep_batch_supported(v)) return v;
+  return 1;
 }
 
 lbm_status create_impl(const lbm_params* cases, const int64_t* budgets, int32_t n, void* stream,
@@ -168,6 +253,7 @@ lbm_status create_impl(const lbm_params* cases, const int64_t* budgets, int32_t 
   auto bud = [&](int i) { return budgets && budgets[i] >= 0 ? budgets[i] : INT64_MAX; };
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return bud(a) > bud(c); });
   b->slot_of_case.assign(n, 0);
+  b->case_cur.assign(n, 0);
   for (int k = 0; k < n; ++k) {
     b->slot_of_case[order[k]] = k;
     b->params.push_back(cases[order[k]]);
@@ -241,7 +327,7 @@ lbm_status create_impl(const lbm_params* cases, const int64_t* budgets, int32_t 
   }
   if ((st = dmalloc(b, (void**)&b->d_cases, sizeof(lbm::CaseArgs) * n)) != LBM_OK) return st;
   if ((st = dmalloc(b, (void**)&b->d_tiles, sizeof(int2) * ntiles_max)) != LBM_OK) return st;
-  return set_variant(b, 1);
+  return set_variant(b, batch_default_variant(b));
 }
 
 lbm_status check_case(const lbm_batch* b, int32_t c) {
@@ -261,9 +347,17 @@ double time_variant(lbm_batch* b, int v, int steps) {
     return 1e30;
   }
   const int active = b->n;
-  for (int i = 0; i < 4; ++i) (void)enqueue(b, active, b->stream);
+  for (int i = 0; i < 12;) {
+    const int k = group(b, 12 - i);
+    (void)enqueue(b, active, b->stream, k);
+    i += k;
+  }
   (void)hipEventRecord(e0, b->stream);
-  for (int i = 0; i < steps; ++i) (void)enqueue(b, active, b->stream);
+  for (int i = 0; i < steps;) {
+    const int k = group(b, steps - i);
+    (void)enqueue(b, active, b->stream, k);
+    i += k;
+  }
   (void)hipEventRecord(e1, b->stream);
   float ms = 1e30f;
   if (hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
@@ -324,6 +418,18 @@ void lbm_batch_destroy(lbm_batch* b) { free_batch(b); }
 
 int32_t lbm_batch_variant(const lbm_batch* b) { return b ? b->variant : 0; }
 
+lbm_status lbm_batch_set_variant(lbm_batch* b, int32_t variant) {
+  if (!b) return lbm::set_error(LBM_ERR_INVALID_ARG, "batch is NULL");
+  if (!batch_capable(variant)) {
+    char m[64];
+    snprintf(m, sizeof m, "variant %d cannot run an ensemble", (int)variant);
+    return lbm::set_error(LBM_ERR_INVALID_ARG, m);
+  }
+  lbm_status st = fold(b, b->stream);
+  if (st != LBM_OK) return st;
+  return set_variant(b, variant);
+}
+
 lbm_status lbm_batch_step(lbm_batch* b, int64_t n) {
   if (!b || n < 0) return lbm::set_error(LBM_ERR_INVALID_ARG, "bad lbm_batch_step arguments");
   int64_t i = 0;
@@ -334,9 +440,10 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n) {
     const int64_t seg = std::min(n - i, b->budget[active - 1] - b->step);
     int64_t j = 0;
     while (j < seg && b->pending != 0) {
-      lbm_status st = enqueue(b, active, b->stream);
+      const int k = group(b, seg - j);
+      lbm_status st = enqueue(b, active, b->stream, k);
       if (st != LBM_OK) return st;
-      ++j;
+      j += k;
     }
     while (seg - j >= lbm::kRing) {
       const auto key = std::make_pair(b->cur, active);
@@ -347,10 +454,16 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n) {
         const int64_t step0 = b->step;
         BTRY(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
         lbm_status st = LBM_OK;
-        for (int k = 0; k < lbm::kRing && st == LBM_OK; ++k) st = enqueue(b, active, b->capture_stream);
+        int launches = 0;
+        for (int k = 0; k < lbm::kRing && st == LBM_OK; ++launches) {
+          const int g = group(b, lbm::kRing - k);
+          st = enqueue(b, active, b->capture_stream, g);
+          k += g;
+        }
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(b->capture_stream, &g);
         b->cur = cur0;
+        for (int c = 0; c < active; ++c) b->case_cur[c] = cur0;
         b->step = step0;
         b->pending = 0;
         if (st != LBM_OK) {
@@ -362,15 +475,19 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n) {
         const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e2 != hipSuccess) return lbm::set_error(LBM_ERR_HIP, hipGetErrorString(e2));
-        it = b->graphs.emplace(key, ex).first;
+        it = b->graphs.emplace(key, std::make_pair(ex, launches & 1)).first;
       }
-      BTRY(hipGraphLaunch(it->second, b->stream));
+      BTRY(hipGraphLaunch(it->second.first, b->stream));
+      b->cur ^= it->second.second;
+      for (int c = 0; c < active; ++c) b->case_cur[c] = b->cur;
       b->step += lbm::kRing;
       j += lbm::kRing;
     }
-    for (; j < seg; ++j) {
-      lbm_status st = enqueue(b, active, b->stream);
+    while (j < seg) {
+      const int k = group(b, seg - j);
+      lbm_status st = enqueue(b, active, b->stream, k);
       if (st != LBM_OK) return st;
+      j += k;
     }
     i += seg;
   }
@@ -441,9 +558,9 @@ lbm_status lbm_batch_fields(lbm_batch* b, int32_t c, float* rho, float* ux, floa
   if (st != LBM_OK) return st;
   const int k = b->slot_of_case[c];
   const lbm::CaseArgs& ca = b->hcase[k];
-  // a case that stopped at its budget holds its state in the buffer matching
-  // the parity of its own step count (every case starts in buf[0])
-  const float* state = ca.buf[(int)(case_steps(b, k) & 1)];
+  // a case that stopped at its budget holds its state in the buffer of its
+  // last launch (every case starts in buf[0])
+  const float* state = ca.buf[b->case_cur[k]];
   const size_t n = (size_t)ca.g.nx * ca.g.ny;
   if (on_device) {
     BTRY(lbm::launch_fields(state, ca.g, rho, ux, uy, b->stream));
@@ -468,7 +585,7 @@ lbm_status lbm_batch_get_populations(lbm_batch* b, int32_t c, void* buf, int dty
   if (!buf || (dtype != 0 && dtype != 1)) return lbm::set_error(LBM_ERR_INVALID_ARG, "bad buffer or dtype");
   const int k = b->slot_of_case[c];
   const lbm::CaseArgs& ca = b->hcase[k];
-  const float* own = ca.buf[(int)(case_steps(b, k) & 1)];
+  const float* own = ca.buf[b->case_cur[k]];
   const size_t bytes = (size_t)9 * ca.g.nx * ca.g.ny * (dtype ? 8 : 4);
   if (on_device) {
     BTRY(lbm::launch_pack(own, ca.g, buf, dtype, b->stream));

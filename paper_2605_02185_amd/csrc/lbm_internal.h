@@ -115,7 +115,8 @@ struct CaseArgs {
   float* buf[2];        // ping-pong population buffers (shifted storage)
   Geometry g;
   Physics p;
-  Tiling t;             // remap_xcd must be 0
+  Tiling t;             // one-step tiling (remap_xcd must be 0)
+  Tiling tm;            // multi-step tiling of the ensemble's variant
   double2* partial;     // slot 0 of this case's force contributions; step j
                         // of the ring at partial + j * partial_stride
   int* bad;             // watchdog slot of this case
@@ -142,6 +143,11 @@ int default_variant(int64_t nodes);
 hipError_t launch_step(const StepArgs& a, int v, hipStream_t s);
 hipError_t launch_step_batch(const CaseArgs* cases, const int2* tiles, int ntiles, int cur, int slot,
                              int partial_stride, int v, hipStream_t s);
+// Multi-step ensemble launch: boundary tasks first, then interior tasks
+// (see multistep_batch_kernel); only variants multistep_batch_supported.
+bool multistep_batch_supported(int v);
+hipError_t launch_multistep_batch(const CaseArgs* cases, const int2* gen_tasks, int n_gen, const int2* bulk_tasks,
+                                  int n_bulk, int cur, int slot, int partial_stride, int v, hipStream_t s);
 hipError_t launch_force_reduce_batch(const CaseArgs* cases, int ncases, int count, int partial_stride,
                                      hipStream_t s);
 hipError_t launch_force_reduce(const double2* partials, int nnodes, int count, double* hist,

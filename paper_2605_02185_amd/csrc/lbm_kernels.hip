@@ -1118,6 +1118,45 @@ __global__ __launch_bounds__(256) void step_batch_kernel(const CaseArgs* __restr
   process_tile<TY, VX, NT>(a, ct.y % c.t.ntx, ct.y / c.t.ntx);
 }
 
+// S steps of a whole ensemble in one launch: wave w takes task w of the
+// boundary list (w < n_gen) or task w - n_gen of the interior list, each a
+// (case, code) pair: code = seg * ntx + strip of the case's multi-step
+// tiling for an interior segment, (seg * ntx + strip) * pieces + piece for
+// a boundary piece.  The wave then runs the single-lattice wave code
+// with that case's buffers, geometry, physics and force slots, so every case
+// evolves bit for bit as it would alone.  Boundary pieces come first, as in
+// multistep_kernel.
+template <bool NT, int H, int SUB, int S>
+__global__ __launch_bounds__(256) void multistep_batch_kernel(const CaseArgs* __restrict__ cases,
+                                                              const int2* __restrict__ gen_tasks, int n_gen,
+                                                              const int2* __restrict__ bulk_tasks, int n_bulk,
+                                                              int cur, int slot, int partial_stride) {
+  constexpr int per = (H + SUB - 1) / SUB;
+  const int wave = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (wave >= n_gen + n_bulk) return;
+  const bool general = wave < n_gen;
+  const int2 task = general ? gen_tasks[wave] : bulk_tasks[wave - n_gen];
+  const int ci = __builtin_amdgcn_readfirstlane(task.x);
+  const int code = __builtin_amdgcn_readfirstlane(task.y);
+  const CaseArgs& c = cases[ci];
+  StepArgs a{};  // no closure, no boundary list (the task names the segment)
+  a.A = c.buf[cur];
+  a.B = c.buf[cur ^ 1];
+  a.g = c.g;
+  a.p = c.p;
+  a.t = c.tm;
+  a.partial = c.partial + (size_t)slot * partial_stride;
+  a.partial2 = a.partial + partial_stride;
+  a.partial3 = S >= 3 ? a.partial2 + partial_stride : nullptr;
+  a.partial4 = S >= 4 ? a.partial3 + partial_stride : nullptr;
+  a.bad = c.bad;
+  a.slot = slot;
+  if (general)
+    general_wave_n<NT, SUB, S, kEither>(a, code / per, code % per);
+  else
+    bulk_wave_n<NT, H, S, kEither>(a, code % a.t.ntx, code / a.t.ntx);
+}
+
 // Folds row blockIdx.x of the per-node force contributions into the FP64
 // history at step *dev_step + blockIdx.x.  The order is fixed: thread t sums
 // nodes t, t+256, ... in turn, each wave reduces its 64 sums by a butterfly
@@ -1345,6 +1384,36 @@ hipError_t launch_step_batch(const CaseArgs* cases, const int2* tiles, int ntile
 #undef LBM_CASE
   return hipErrorInvalidValue;
 }
+
+// Multi-step variants the ensemble runs (instantiated below).
+#define LBM_TB_LIST(X) X(8, 2, 3) X(8, 4, 3) X(8, 2, 4) X(8, 4, 4) X(8, 8, 4)
+
+bool multistep_batch_supported(int v) {
+  if (v < 1 || v > num_variants()) return false;
+  const Variant& var = variant(v);
+  if (var.nontemporal || var.steps < 3) return false;
+#define LBM_TB_HAS(H, SUB, S) if (var.tile_y == H && var.sub == SUB && var.steps == S) return true;
+  LBM_TB_LIST(LBM_TB_HAS)
+#undef LBM_TB_HAS
+  return false;
+}
+
+hipError_t launch_multistep_batch(const CaseArgs* cases, const int2* gen_tasks, int n_gen, const int2* bulk_tasks,
+                                  int n_bulk, int cur, int slot, int partial_stride, int v, hipStream_t s) {
+  if (!multistep_batch_supported(v)) return hipErrorInvalidValue;
+  const Variant& var = variant(v);
+  const dim3 grid((unsigned)((n_gen + n_bulk + 3) / 4)), block(256);
+#define LBM_TB_LAUNCH(H, SUB, S)                                                                  \
+  if (var.tile_y == H && var.sub == SUB && var.steps == S) {                                       \
+    hipLaunchKernelGGL((multistep_batch_kernel<false, H, SUB, S>), grid, block, 0, s, cases, gen_tasks, \
+                       n_gen, bulk_tasks, n_bulk, cur, slot, partial_stride);                      \
+    return hipGetLastError();                                                                      \
+  }
+  LBM_TB_LIST(LBM_TB_LAUNCH)
+#undef LBM_TB_LAUNCH
+  return hipErrorInvalidValue;
+}
+#undef LBM_TB_LIST
 
 hipError_t launch_force_reduce_batch(const CaseArgs* cases, int ncases, int count, int partial_stride,
                                      hipStream_t s) {

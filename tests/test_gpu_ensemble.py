@@ -54,6 +54,55 @@ def test_mixed_ensemble_matches_separate_runs_bitwise():
             assert np.array_equal(a, c), i
 
 
+MULTI = ["t3_h8_s2", "t3_h8_s4", "t4_h8_s2", "t4_h8_s4", "t4_h8_s8"]
+
+
+@pytest.mark.parametrize("name", MULTI)
+def test_multistep_ensemble_matches_separate_runs_bitwise(name):
+    """Three or four steps per launch over every active case: budgets that
+    are not multiples of the step count (the rest runs one step per launch),
+    a 96-step graph replay and calls of odd lengths still give every case
+    the bits of its own run."""
+    v = {lbm.variant_name(i): i for i in range(1, lbm.num_variants() + 1)}[name]
+    cases = [
+        dict(channel(6, u=0.05, re=80), tau=0.62),
+        dict(channel(9, u=0.05, re=150), tau=0.58, wall=lbm.WALL_PERIODIC, collision=lbm.COLLISION_MRT,
+             s_rates=(1, 1.1, 1.1, 1, 1.1, 1, 1.1, 0, 0)),
+        dict(channel(7, u=0.04, re=60), tau=0.7, wall=lbm.WALL_MOVING_BB, outlet_mode=lbm.OUTLET_COPY_UNKNOWN,
+             bounce=lbm.BOUNCE_FULLWAY),
+        dict(nx=300, ny=64, u_in=0.03, tau=0.7, wall=lbm.WALL_NEBB),
+        dict(nx=130, ny=77, tau=0.6, u_in=0.0, x_periodic=True, wall=lbm.WALL_PERIODIC, perturb_amp=0.0),
+        dict(channel(8, u=0.05), tau=0.6, bounce=lbm.BOUNCE_INTERP),
+    ]
+    budgets = [300, 137, 251, 64, 200, 299]
+    note(f"ensemble of {len(cases)} cases on {name}, budgets {budgets}")
+    ens = lbm.Ensemble([lbm.make_params(**kw) for kw in cases], budgets=budgets)
+    ens.set_variant(v)
+    assert ens.variant == v
+    ens.step(5)
+    ens.step(150)
+    ens.step(1)
+    ens.step(400)  # beyond every budget
+    ens.sync()
+    for i, (kw, b) in enumerate(zip(cases, budgets)):
+        steps, bad = ens.info(i)
+        assert (steps, bad) == (b, 0)
+        f_alone, forces_alone = _alone(kw, b)
+        assert np.array_equal(ens.get_populations(i, np.float64), f_alone), i
+        for a, c in zip(ens.forces(i), forces_alone):
+            if a is not None:
+                assert np.array_equal(a, c), i
+
+
+def test_ensemble_rejects_variants_it_cannot_run():
+    ens = lbm.Ensemble([lbm.make_params(**dict(channel(6), tau=0.6))])
+    xcd = {lbm.variant_name(i): i for i in range(1, lbm.num_variants() + 1)}["v1_ty1_xcd_nt"]
+    with pytest.raises(lbm.LbmError):
+        ens.set_variant(xcd)
+    with pytest.raises(lbm.LbmError):
+        ens.set_variant(lbm.num_variants() + 1)
+
+
 @pytest.mark.parametrize("mrt", [False, True])
 def test_full_ensemble_of_64_channels_matches_separate_runs(mrt):
     """The 64-case ensemble (D in 8..32, Re in [60, 200], U = 0.05, tau from

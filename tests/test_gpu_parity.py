@@ -238,6 +238,8 @@ def _two_step_cases():
         dict(nx=3, ny=3, tau=0.8, u_in=0.05, wall=lbm.WALL_NEBB),
         dict(channel(6, u=0.06), tau=0.52, collision=lbm.COLLISION_MRT,
              s_rates=(1, 1.1, 1.1, 1, 1.1, 1, 1.1, 0, 0)),
+        dict(channel(9, u=0.05, re=150), tau=0.58, wall=lbm.WALL_PERIODIC, collision=lbm.COLLISION_MRT,
+             s_rates=(1, 1.1, 1.1, 1, 1.1, 1, 1.1, 0, 0)),
     ]
     return cases
 
