@@ -372,11 +372,11 @@ lbm_status lbm_closure_set_filter(lbm_ctx* ctx, float beta, int32_t taper);
 /* Evaluate the network only every `interval` steps (a divisor of 96: 1, 2,
  * 3, 4, 6, 8, 12, 16, 24, 32, 48 or 96; default 1) and apply the held
  * residual in between, at the steps whose
- * index since lbm_create is a multiple of `interval`.  With an even interval
- * the context keeps its two-step launches (pairs that start on an evaluation
- * step), the held residual entering both steps of a pair; the results are
- * the same bit for bit as with one step per launch.  beta applies per
- * evaluation. */
+ * index since lbm_create is a multiple of `interval`.  A launch of the
+ * variant's two, three or four steps runs wherever no evaluation falls
+ * strictly inside it (else single steps), the held residual entering every
+ * step of the launch; the results are the same bit for bit as with one step
+ * per launch.  beta applies per evaluation. */
 lbm_status lbm_closure_set_interval(lbm_ctx* ctx, int32_t interval);
 
 /* Residuals the closure computes from the current state, host [nb][3]. */

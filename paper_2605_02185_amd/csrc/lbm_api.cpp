@@ -496,20 +496,22 @@ namespace {
 // of its interval.
 bool closure_due(const lbm_ctx* c) { return c->mlp && c->step % c->closure_interval == 0; }
 
-// Two steps fit in one launch when the variant takes two, the ring has room
-// and no closure evaluation falls between them.
-bool pairable(const lbm_ctx* c) {
-  if (lbm::variant(c->variant).steps != 2 || c->pending + 2 > lbm::kRing) return false;
-  return !c->mlp || (c->closure_interval % 2 == 0 && (c->step + 1) % c->closure_interval != 0);
+// Steps t .. t+k-1 share one launch only if no closure evaluation falls
+// strictly inside them (an evaluation precedes each step whose index is a
+// multiple of the interval and reads the state before it); every level of a
+// multi-step launch applies the residuals held since the last evaluation, as
+// k one-step launches would.
+bool closure_allows(const lbm_ctx* c, int k) {
+  if (!c->mlp) return true;
+  return c->closure_interval - c->step % c->closure_interval >= k;
 }
 
 // Steps of the next launch, with `left` steps still to go: the variant's two,
-// three or four when they fit (more than two only without a learned
-// closure), else one.
+// three or four when they fit in the force ring and between closure
+// evaluations, else one.
 int group(const lbm_ctx* c, int64_t left) {
   const int s = lbm::variant(c->variant).steps;
-  if (s >= 3 && left >= s && !c->mlp && c->pending + s <= lbm::kRing) return s;
-  if (s == 2 && left >= 2 && pairable(c)) return 2;
+  if (s >= 2 && left >= s && c->pending + s <= lbm::kRing && closure_allows(c, s)) return s;
   return 1;
 }
 
@@ -545,6 +547,7 @@ lbm_status enqueue_step(lbm_ctx* c, hipStream_t s, int k = 1) {
                                   c->closure_taper, c->d_resid, s));
     }
     a.closure = c->d_resid;
+    a.closure_mask = c->closure_mask;
   }
   HIP_TRY(lbm::launch_step(a, v, s));
   c->cur ^= 1;

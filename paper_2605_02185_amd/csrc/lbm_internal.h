@@ -106,6 +106,7 @@ struct StepArgs {
   const int* gen;               // multi-step launches: segments (seg * ntx + strip) that are not interior
   int n_gen;
   const float* closure;         // learned-closure residuals [boundary node][3], or null
+  int closure_mask;             // boundaries the closure refines: 1 top, 2 bottom, 4 outlet
   int* bad;                     // watchdog: min ring slot with a bad density
   int slot;                     // ring slot of this step
 };

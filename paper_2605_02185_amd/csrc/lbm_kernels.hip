@@ -311,11 +311,10 @@ __device__ __forceinline__ void inlet_bc(const Physics& p, bool corner, float (&
 // bounce-back f*_opp(k)(x) enters the solid node now and comes back reversed
 // one step later; its whole exchange, 2 c_opp(k) f*_opp(k)(x), is booked
 // now.  `own` holds the node's post-collision f* (read by the interpolated
-// and full-way modes).  Written to the node's fixed slot of this step's
-// contributions.
-__device__ __forceinline__ void link_force(const Geometry& geo, double2* __restrict__ partial, int x, int y,
-                                           uint16_t fl, const float (&g)[9], const float (&own)[9],
-                                           const Physics& p) {
+// and full-way modes).  Written to the node's fixed slot `li` of this step's
+// contributions (its position in the list of link nodes).
+__device__ __forceinline__ void link_force(double2* __restrict__ partial, int li, uint16_t fl, const float (&g)[9],
+                                           const float (&own)[9], const Physics& p) {
   double Fx = 0.0, Fy = 0.0;
 #pragma unroll
   for (int k = 1; k < 9; ++k)
@@ -335,7 +334,7 @@ __device__ __forceinline__ void link_force(const Geometry& geo, double2* __restr
         Fy -= 2.0 * (double)CY[k] * fk;
       }
     }
-  partial[link_slot(geo, x, y)] = make_double2(Fx, Fy);
+  partial[li] = make_double2(Fx, Fy);
 }
 
 // Learned-closure residuals (when enabled) on the three missing populations
@@ -357,8 +356,39 @@ __device__ __forceinline__ void closure_row(const StepArgs& a, int x, int y, flo
   g[5] = top ? g[5] : g[5] + r2;
 }
 
-__device__ __forceinline__ void closure_outlet(const StepArgs& a, int y, float (&g)[9]) {
+// The same wall-row residuals as closure_row, taken from registers: rt and rb
+// hold this lane's entries for the top and bottom rows (closure_rows_load).
+__device__ __forceinline__ void closure_row_regs(const StepArgs& a, bool top, const float (&rt)[3],
+                                                 const float (&rb)[3], float (&g)[9]) {
   if (!a.closure) return;
+  const float r0 = top ? rt[0] : rb[0], r1 = top ? rt[1] : rb[1], r2 = top ? rt[2] : rb[2];
+  g[4] = top ? g[4] + r0 : g[4];
+  g[7] = top ? g[7] + r1 : g[7];
+  g[8] = top ? g[8] + r2 : g[8];
+  g[2] = top ? g[2] : g[2] + r0;
+  g[6] = top ? g[6] : g[6] + r1;
+  g[5] = top ? g[5] : g[5] + r2;
+}
+
+// Column x's residuals on the top and bottom rows, read when `need` (the
+// caller's rows include a wall row); zeros without a closure.  Columns
+// outside 1 .. nx-2, which have none, read column 1 or nx-2 and never apply
+// them.
+__device__ __forceinline__ void closure_rows_load(const StepArgs& a, bool need, int x, float (&rt)[3],
+                                                  float (&rb)[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) rt[c] = rb[c] = 0.0f;
+  if (!a.closure || !need) return;
+  const int i = min(max(x, 1), a.g.nx - 2) - 1;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    rt[c] = a.closure[3 * i + c];
+    rb[c] = a.closure[3 * (a.g.nx - 2 + i) + c];
+  }
+}
+
+__device__ __forceinline__ void closure_outlet(const StepArgs& a, int y, float (&g)[9]) {
+  if (!a.closure || !(a.closure_mask & 4)) return;
   const float* r = a.closure + 3 * (2 * (a.g.nx - 2) + (y - 1));
   g[3] += r[0];
   g[6] += r[1];
@@ -433,7 +463,7 @@ __device__ __forceinline__ void general_update(const StepArgs& a, int x, int y, 
 #pragma unroll
       for (int k = 0; k < 9; ++k) own[k] = load(a.A, a.g, k, x, y);
     }
-    link_force(a.g, a.partial, x, y, fl, g, own, a.p);
+    link_force(a.partial, link_slot(a.g, x, y), fl, g, own, a.p);
   }
   collide_t<COLL>(g, a.p, out, bad);
 }
@@ -542,6 +572,166 @@ __device__ __forceinline__ void bulk_vec(const StepArgs& a, int x0, int y, bool&
   }
 }
 
+// ------------------------------------------------ boundary code on registers
+// The boundary treatment of a node from values already in registers, shared
+// by the one-step kernel's boundary waves and every level of the multi-step
+// kernels' boundary waves.
+
+// Value of the lane below (lane l gets lane l-1) and above (lane l gets
+// l+1), by DPP whole-wave shifts (a VALU move, no LDS permute).  The lane at
+// the wave's end keeps its own value; only halo lanes read it.
+__device__ __forceinline__ float from_left(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_right(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+// What the first level of a boundary wave reads from memory for node (x, y):
+// the pulled populations f*_k(x - c_k) before any boundary treatment (with
+// the periodic wrap-arounds; a source outside the lattice reads the node
+// itself, discarded later), the node's own f*_k for k = 1..8 (own[k - 1];
+// f*_0 is pl[0]) and its raw flag and link-list entries (meaningful inside
+// the cylinder rectangle only).  Every address is valid for every lane and
+// nothing loaded is used here, so a wave issues the loads of the next row
+// before it works on the current one and waits for them only at the end of
+// that work.
+struct RowIn {
+  float pl[9], own[8];
+  int fl, li;
+};
+
+__device__ __forceinline__ void row_load(const StepArgs& a, int x, int y, RowIn& r) {
+  const int nx = a.g.nx, ny = a.g.ny;
+  const int cx = min(max(x, 0), nx - 1), cy = min(max(y, 0), ny - 1);
+  const float* __restrict__ A = a.A;
+  const uint32_t P = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    int sx = x - CX[k], sy = y - CY[k];
+    if (a.p.x_periodic) sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+    if (a.p.wall == kWallPeriodic) sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+    const bool ok = sx >= 0 && sx < nx && sy >= 0 && sy < ny;
+    r.pl[k] = A[(uint32_t)k * P + (uint32_t)(ok ? sy : cy) * Wp + (uint32_t)(ok ? sx : cx)];
+    if (k > 0) r.own[k - 1] = A[(uint32_t)k * P + (uint32_t)cy * Wp + (uint32_t)cx];
+  }
+  r.fl = 0;
+  r.li = -1;
+  if (a.g.flags) {  // a cylinder: both tables exist
+    const int i = min(max(y - a.g.ry0, 0), a.g.rh - 1) * a.g.rw + min(max(x - a.g.rx0, 0), a.g.rw - 1);
+    r.fl = a.g.flags[i];
+    r.li = a.g.link_index[i];
+  }
+}
+
+// Post-collision populations of node (x, y) one level up, from registers:
+// c[k] = f*_k(x - c_k) of the level below before any boundary treatment, w1
+// the node's own populations on that level, w0 and w2 those of the rows below
+// and above (x-neighbours in the adjacent lanes; read for the interpolated
+// bounce-back on levels above the first, L1 false), fl_raw and li the
+// node's raw flag and link-list entries, rt and rb this lane's wall-row
+// closure residuals.  The same steps as general_update; link forces go to
+// `partial`.  On the first level (L1) the interpolated bounce-back reads
+// f*_opp(k)(x + c_k) from memory (lanes at the wave's edges have no
+// neighbour lane) and lanes outside the lattice get zeros; on the others
+// those lanes leave `out` unset (nothing reads it).
+template <int COLL, bool L1>
+__device__ __forceinline__ void update_regs(const StepArgs& a, double2* __restrict__ partial, int x, int y,
+                                            bool active, bool owner, const float (&c)[9], const float (&w0)[9],
+                                            const float (&w1)[9], const float (&w2)[9], int fl_raw, int li,
+                                            const float (&rt)[3], const float (&rb)[3], float (&out)[9],
+                                            bool& bad) {
+  const int nx = a.g.nx, ny = a.g.ny;
+  const bool inr = in_rect(a.g, x, y);
+  const bool special = active && (x == 0 || x >= nx - 1 || y == 0 || y == ny - 1 || inr);
+  bool b = false;
+  if (!__any(special)) {
+    if (active) collide_t<COLL>(c, a.p, out, b);
+  } else {
+    const bool open_x = !a.p.x_periodic;
+    const bool outlet = active && open_x && x == nx - 1;
+    const bool corner_y = a.p.wall != kWallPeriodic && (y == 0 || y == ny - 1);
+    const uint16_t fl = active && inr ? (uint16_t)fl_raw : 0;
+    // interpolated bounce-back needs f*_opp(k) at x + c_k (only where the
+    // wave has links)
+    float bh[9];
+    const bool interp = a.p.interp_bb && __any(fl >> 1);
+    if (interp) {
+      if (L1) {
+        bh[0] = 0.0f;
+#pragma unroll
+        for (int k = 1; k < 9; ++k)  // the cylinder keeps two nodes from every edge: x + c_k is inside
+          bh[k] = ((fl >> k) & 1) ? load(a.A, a.g, OPP[k], x + CX[k], y + CY[k]) : 0.0f;
+      } else {
+        bh[0] = 0.0f;
+        bh[1] = from_right(w1[3]);
+        bh[2] = w2[4];
+        bh[3] = from_left(w1[1]);
+        bh[4] = w0[2];
+        bh[5] = from_right(w2[7]);
+        bh[6] = from_left(w2[8]);
+        bh[7] = from_left(w0[5]);
+        bh[8] = from_right(w0[6]);
+      }
+    }
+    float g[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      if (k > 0 && ((fl >> k) & 1) && !a.p.full_bb) {  // bounce-back on the cylinder
+        if (interp) {
+          const float q = a.g.q[8 * li + k - 1];
+          g[k] = bfl(q, w1[OPP[k]], bh[k], w1[k]);
+        } else {
+          g[k] = w1[OPP[k]];
+        }
+        continue;
+      }
+      int sx = x - CX[k], sy = y - CY[k];
+      if (a.p.x_periodic) sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+      if (a.p.wall == kWallPeriodic) sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+      g[k] = (sx >= 0 && sx < nx && sy >= 0 && sy < ny) ? c[k] : 0.0f;
+    }
+    const bool wall_row = a.p.wall != kWallPeriodic && (y == 0 || y == ny - 1);
+    const bool wall_x = a.p.x_periodic || (x >= 1 && x <= nx - 2);
+    if (active && wall_row && wall_x) {
+      wall_bc(a.p, y == ny - 1, w1, g);
+      closure_row_regs(a, y == ny - 1, rt, rb, g);
+    }
+    // Eq. 13: the corrected populations of x = nx-2 are the left lane's g
+    if (__any(outlet)) {
+      float G[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) G[k] = from_left(g[k]);
+      if (outlet) {
+        if (a.p.outlet_mode == kOutletCopyUnknown && !corner_y) {
+          g[3] = G[3];
+          g[6] = G[6];
+          g[7] = G[7];
+          closure_outlet(a, y, g);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) g[k] = G[k];
+        }
+      }
+    }
+    if (active) {
+      if (fl & kSolid) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) out[k] = a.p.full_bb ? g[OPP[k]] : w1[k];
+      } else {
+        if (open_x && x == 0) inlet_bc(a.p, corner_y, g);
+        if ((fl >> 1) && owner) link_force(partial, li, fl, g, w1, a.p);
+        collide_t<COLL>(g, a.p, out, b);
+      }
+    }
+  }
+  if (L1 && !active) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) out[k] = 0.0f;
+  }
+  bad |= b && owner;
+}
+
 // Records a failed density check of step `slot` once per wave (one atomic
 // per wave rather than per node keeps a diverged lattice, where every node
 // fails, from serialising on the flag).  Every lane of the wave must call it.
@@ -572,7 +762,11 @@ __device__ __forceinline__ int remap_xcd_rows(int id, int ntx, int nty) {
 }
 
 // One tile = tile_x = 256 * VX consecutive nodes of TY rows; lane t of the
-// block owns nodes x0 .. x0+VX-1 with x0 = tile origin + VX t.
+// block owns nodes x0 .. x0+VX-1 with x0 = tile origin + VX t.  Waves with a
+// node that needs the boundary code load everything it may read at once and
+// apply it on registers (update_regs) when each lane holds one node and the
+// outlet's left neighbour is in the same wave; otherwise node by node
+// (general_node).
 template <int TY, int VX, bool NT>
 __device__ __forceinline__ void process_tile(const StepArgs& a, int bx, int by) {
   const int nx = a.g.nx, ny = a.g.ny;
@@ -586,9 +780,23 @@ __device__ __forceinline__ void process_tile(const StepArgs& a, int bx, int by) 
                       x0 < a.g.rx0 + a.g.rw;
     const bool special = active && (x0 == 0 || x0 + VX - 1 >= nx - 1 || y == 0 || y == ny - 1 || rect);
     if (__any(special)) {
+      if (VX == 1 && (a.p.x_periodic || ((nx - 1) & 63) != 0)) {
+        RowIn in;
+        row_load(a, x0, y, in);
+        float rt[3], rb[3];
+        closure_rows_load(a, y == 0 || y == ny - 1, x0, rt, rb);
+        float own[9], out[9];
+        own[0] = in.pl[0];
 #pragma unroll
-      for (int j = 0; j < VX; ++j)
-        if (active && x0 + j < nx) general_node<NT>(a, x0 + j, y, bad);
+        for (int k = 1; k < 9; ++k) own[k] = in.own[k - 1];
+        update_regs<kEither, true>(a, a.partial, x0, y, active, true, in.pl, own, own, own, in.fl, in.li, rt, rb,
+                                   out, bad);
+        if (active) store9<NT>(a.B, (uint32_t)a.g.plane, (uint32_t)y * (uint32_t)a.g.pitch + (uint32_t)x0, out);
+      } else {
+#pragma unroll
+        for (int j = 0; j < VX; ++j)
+          if (active && x0 + j < nx) general_node<NT>(a, x0 + j, y, bad);
+      }
     } else if (active) {
       if constexpr (VX == 1)
         bulk_node<NT>(a, x0, y, bad);
@@ -627,159 +835,10 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
 //
 // Segments whose first-step nodes are all plain bulk fluid (interior_segment)
 // run a lean, fully unrolled path (bulk_wave); the others run the boundary
-// code of the one-step kernel on registers (general_wave, first_update,
-// second_update).  Without x-periodicity the strips are aligned to the right
+// code of the one-step kernel on registers (general_wave_n, update_regs).
+// Without x-periodicity the strips are aligned to the right
 // edge, so the outlet column is always lane 62 and the column it copies
 // (nx-2) lane 61.
-// Value of the lane below (lane l gets lane l-1) and above (lane l gets
-// l+1), by DPP whole-wave shifts (a VALU move, no LDS permute).  The lane at
-// the wave's end keeps its own value; only halo lanes read it.
-__device__ __forceinline__ float from_left(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xf, 0xf, false));
-}
-__device__ __forceinline__ float from_right(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130, 0xf, 0xf, false));
-}
-
-// The nine pulled values of a bulk node at (x, y) clamped into the interior,
-// so that the addresses are valid for every lane; used only where the node
-// turns out to be bulk fluid.
-__device__ __forceinline__ void prefetch_bulk(const StepArgs& a, int x, int y, float (&v)[9]) {
-  const int cx = min(max(x, 1), a.g.nx - 2), cy = min(max(y, 1), a.g.ny - 2);
-  const float* __restrict__ A = a.A;
-  const uint32_t P = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
-  const uint32_t o = (uint32_t)cy * Wp + (uint32_t)cx;
-  v[0] = A[o];
-  v[1] = A[P + o - 1];
-  v[2] = A[2 * P + o - Wp];
-  v[3] = A[3 * P + o + 1];
-  v[4] = A[4 * P + o + Wp];
-  v[5] = A[5 * P + o - Wp - 1];
-  v[6] = A[6 * P + o - Wp + 1];
-  v[7] = A[7 * P + o + Wp + 1];
-  v[8] = A[8 * P + o + Wp - 1];
-}
-
-// f*(t+1) at (x, y) for one lane; `active` false gives zeros (outside the
-// lattice), `owner` selects who records forces and density failures.
-template <int COLL = kEither>
-__device__ __forceinline__ void first_update(const StepArgs& a, int x, int y, bool active, bool owner,
-                                             const float (&pre)[9], float (&out)[9], bool& bad) {
-  const int nx = a.g.nx, ny = a.g.ny;
-  const bool special = active && (x == 0 || x >= nx - 1 || y == 0 || y == ny - 1 || in_rect(a.g, x, y));
-  bool b = false;
-  if (__any(special)) {
-    if (active) general_update<COLL>(a, x, y, owner, out, b);
-  } else if (active) {
-    collide_t<COLL>(pre, a.p, out, b);  // the bulk pull, loaded ahead
-  }
-  if (!active) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) out[k] = 0.0f;
-  }
-  bad |= b && owner;
-}
-
-// f*(t+2) at (x, y) from f*(t+1) of rows y-1 (w0), y (w1) and y+1 (w2) of
-// this lane's column and its two neighbour lanes (or one level up: f*(t+3)
-// from f*(t+2)).  The same steps as general_update, with the pulled values
-// taken from registers; link forces go to `partial`.  Inactive lanes leave
-// `out` unset (nothing reads it: their node is outside the lattice).
-template <int COLL = kEither>
-__device__ __forceinline__ void second_update(const StepArgs& a, double2* __restrict__ partial, int x, int y,
-                                              bool active, bool owner, const float (&w0)[9],
-                                              const float (&w1)[9], const float (&w2)[9], float (&out)[9],
-                                              bool& bad) {
-  const int nx = a.g.nx, ny = a.g.ny;
-  // f*_k(x - c_k, y - c_k,y): row by c_y, the lane to the left for c_x = +1
-  float c[9];
-  c[0] = w1[0];
-  c[1] = from_left(w1[1]);
-  c[2] = w0[2];
-  c[3] = from_right(w1[3]);
-  c[4] = w2[4];
-  c[5] = from_left(w0[5]);
-  c[6] = from_right(w0[6]);
-  c[7] = from_right(w2[7]);
-  c[8] = from_left(w2[8]);
-  const bool special = active && (x == 0 || x >= nx - 1 || y == 0 || y == ny - 1 || in_rect(a.g, x, y));
-  bool b = false;
-  if (!__any(special)) {
-    if (active) collide_t<COLL>(c, a.p, out, b);
-    bad |= b && owner;
-    return;
-  }
-  const bool open_x = !a.p.x_periodic;
-  const bool outlet = active && open_x && x == nx - 1;
-  const bool corner_y = a.p.wall != kWallPeriodic && (y == 0 || y == ny - 1);
-  const uint16_t fl = active ? node_flags(a.g, x, y) : 0;
-  // interpolated bounce-back needs f*_opp(k) at x + c_k: the neighbouring
-  // row and lane (wave-wide moves, only where the wave has links)
-  float bh[9];
-  const bool interp = a.p.interp_bb && __any(fl >> 1);
-  if (interp) {
-    bh[0] = 0.0f;
-    bh[1] = from_right(w1[3]);
-    bh[2] = w2[4];
-    bh[3] = from_left(w1[1]);
-    bh[4] = w0[2];
-    bh[5] = from_right(w2[7]);
-    bh[6] = from_left(w2[8]);
-    bh[7] = from_left(w0[5]);
-    bh[8] = from_right(w0[6]);
-  }
-  float g[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    if (k > 0 && ((fl >> k) & 1) && !a.p.full_bb) {  // bounce-back on the cylinder
-      if (interp) {
-        const float q = a.g.q[8 * link_slot(a.g, x, y) + k - 1];
-        g[k] = bfl(q, w1[OPP[k]], bh[k], w1[k]);
-      } else {
-        g[k] = w1[OPP[k]];
-      }
-      continue;
-    }
-    int sx = x - CX[k], sy = y - CY[k];
-    if (a.p.x_periodic) sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
-    if (a.p.wall == kWallPeriodic) sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
-    g[k] = (sx >= 0 && sx < nx && sy >= 0 && sy < ny) ? c[k] : 0.0f;
-  }
-  const bool wall_row = a.p.wall != kWallPeriodic && (y == 0 || y == ny - 1);
-  const bool wall_x = a.p.x_periodic || (x >= 1 && x <= nx - 2);
-  if (active && wall_row && wall_x) {
-    wall_bc(a.p, y == ny - 1, w1, g);
-    closure_row(a, x, y, g);
-  }
-  // Eq. 13: the corrected populations of x = nx-2 are the left lane's g
-  if (__any(outlet)) {
-    float G[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) G[k] = from_left(g[k]);
-    if (outlet) {
-      if (a.p.outlet_mode == kOutletCopyUnknown && !corner_y) {
-        g[3] = G[3];
-        g[6] = G[6];
-        g[7] = G[7];
-        closure_outlet(a, y, g);
-      } else {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) g[k] = G[k];
-      }
-    }
-  }
-  if (!active) return;
-  if (fl & kSolid) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) out[k] = a.p.full_bb ? g[OPP[k]] : w1[k];
-    return;
-  }
-  if (open_x && x == 0) inlet_bc(a.p, corner_y, g);
-  if ((fl >> 1) && owner) link_force(a.g, partial, x, y, fl, g, w1, a.p);
-  collide_t<COLL>(g, a.p, out, b);
-  bad |= b && owner;
-}
-
 // The nine pulled values of bulk node (x, y).
 __device__ __forceinline__ void load_pull(const StepArgs& a, int x, int y, float (&v)[9]) {
   const float* __restrict__ A = a.A;
@@ -843,86 +902,6 @@ __device__ __forceinline__ void bulk_wave(const StepArgs& a, int strip, int seg)
   const uint32_t P = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
 #pragma unroll
   for (int j = 0; j < H; ++j) store9<NT>(a.B, P, (uint32_t)(y0 + j) * Wp + (uint32_t)x, out[j]);
-}
-
-// SUB rows (fewer at the segment's or the lattice's end) of a segment that
-// is not interior, with the boundary code.
-template <bool NT, int SUB>
-__device__ __forceinline__ void general_wave(const StepArgs& a, int segment, int sub) {
-  const int lane = (int)(threadIdx.x & 63);
-  const int S = a.t.ntx, H = a.t.tile_y;
-  const int strip = segment % S, seg = segment / S;
-  const int nx = a.g.nx, ny = a.g.ny;
-  const bool xper = a.p.x_periodic, yper = a.p.wall == kWallPeriodic;
-  const int xs = strip_start(a.g, a.t, xper, strip);
-  const int y0 = seg * H + sub * SUB;
-  if (y0 >= ny) return;
-  const int y1 = min(min(y0 + SUB, seg * H + H), ny);
-  const int ux = xs - 1 + lane;  // column before wrapping
-  const int x = xper ? ((ux % nx) + nx) % nx : ux;
-  const bool col_ok = xper || (ux >= 0 && ux < nx);
-  const bool out_col = lane >= 1 && lane <= kStrip2 && ux >= 0 && ux < nx;
-  const uint32_t P = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
-  float w0[9], w1[9], w2[9], pre[9], pre1[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) w0[k] = w1[k] = w2[k] = 0.0f;
-  auto row_of = [&](int r) { return yper ? (r < 0 ? r + ny : (r >= ny ? r - ny : r)) : r; };
-  prefetch_bulk(a, x, row_of(y0 - 1), pre);
-  prefetch_bulk(a, x, row_of(y0), pre1);
-  bool bad1 = false, bad2 = false;
-  // A rolled loop: unrolled copies of the boundary code (several times the
-  // bulk path's size) crowd the instruction cache the bulk waves on the same
-  // CU run from, which costs the whole launch more than these waves gain.
-#pragma unroll 1
-  for (int r = y0 - 1; r <= y1; ++r) {
-    float nxt[9];
-    prefetch_bulk(a, x, row_of(r + 2), nxt);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      w0[k] = w1[k];
-      w1[k] = w2[k];
-    }
-    const bool row_ok = yper || (r >= 0 && r < ny);
-    const int y = row_of(r);
-    first_update(a, x, y, col_ok && row_ok, out_col && r >= y0 && r < y1, pre, w2, bad1);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      pre[k] = pre1[k];
-      pre1[k] = nxt[k];
-    }
-    if (r > y0) {
-      const int y2 = r - 1;
-      float out[9];
-      second_update(a, a.partial2, x, y2, col_ok, out_col, w0, w1, w2, out, bad2);
-      if (out_col) store9<NT>(a.B, P, (uint32_t)y2 * Wp + (uint32_t)x, out);
-    }
-  }
-  report_bad(a.bad, bad1, a.slot);
-  report_bad(a.bad, bad2, a.slot + 1);
-}
-
-// One launch, two steps.  The first blocks take the boundary sub-segments
-// (segments listed on the host, cut into SUB rows each so that they run
-// alongside the interior ones: 2 rows keep them short where the launch is
-// short, 4 halve their recomputed rows where it is long); the later blocks
-// one segment per wave, in
-// row-major order of (segment, strip), so that the waves in flight at any
-// time cover a narrow band of rows, four neighbouring strips per block.
-// (Orders that keep vertically adjacent segments on one XCD, so that their
-// shared rows are read once into its L2, fetch 30 % fewer bytes but ran
-// 4-10 % slower: the plain order's DRAM locality wins.)
-template <bool NT, int H, int SUB>
-__global__ __launch_bounds__(256) void step2_kernel(StepArgs a) {
-  constexpr int per = (H + SUB - 1) / SUB;
-  const int gen_blocks = (a.n_gen * per + 3) / 4;
-  const int b = (int)blockIdx.x, w = (int)(threadIdx.x >> 6);
-  if (b < gen_blocks) {
-    const int wave = b * 4 + w;
-    if (wave < a.n_gen * per) general_wave<NT, SUB>(a, a.gen[wave / per], wave % per);
-    return;
-  }
-  const int wave = (b - gen_blocks) * 4 + w;
-  if (wave < a.t.ntx * a.t.nty) bulk_wave<NT, H>(a, wave % a.t.ntx, wave / a.t.ntx);
 }
 
 // ------------------------------------------------------- three or four steps
@@ -1007,9 +986,15 @@ __device__ __forceinline__ void bulk_wave_n(const StepArgs& a, int strip, int se
 }
 
 // SUB rows (fewer at the segment's or the lattice's end) of a segment that
-// is not interior, with the boundary code on every level; a rolled loop like
-// general_wave's over the first-level rows r, each level l > 1 following on
-// row r - (l - 1).
+// is not interior, with the boundary code on every level: a rolled loop over
+// the first-level rows r, each level l > 1 following on row r - (l - 1).
+// Each pass issues the loads of row r + 1 first and waits for them only when
+// it moves them into place at its end, so the boundary code of the S levels
+// runs while they are in flight; nothing else in the loop reads memory
+// (except the interpolated bounce-back's wall fractions and the outlet
+// closure's residuals).  Rolled, because unrolled copies of the boundary
+// code crowd the instruction cache that the bulk waves on the same CU run
+// from.
 template <bool NT, int SUB, int S, int COLL>
 __device__ __forceinline__ void general_wave_n(const StepArgs& a, int segment, int sub) {
   constexpr int h = S - 1, W = 64 - 2 * h;
@@ -1027,58 +1012,101 @@ __device__ __forceinline__ void general_wave_n(const StepArgs& a, int segment, i
   const bool col_ok = xper || (ux >= 0 && ux < nx);
   const bool out_col = lane >= h && lane < h + W && ux >= 0 && ux < nx;
   const uint32_t P = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
-  float lv[S - 1][3][9], pre[9], pre1[9];  // rows q-1, q, q+1 of each level below the last
+  auto row_of = [&](int r) { return yper ? (r < 0 ? r + ny : (r >= ny ? r - ny : r)) : r; };
+  auto row_ok = [&](int r) { return yper || (r >= 0 && r < ny); };
+  float rt[3], rb[3];
+  closure_rows_load(a, y0 - h <= 0 || y1 + h - 1 >= ny - 1, x, rt, rb);
+  float lv[S - 1][3][9];  // rows q-1, q, q+1 of each level below the last
 #pragma unroll
   for (int l = 0; l < S - 1; ++l)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
       for (int k = 0; k < 9; ++k) lv[l][j][k] = 0.0f;
-  auto row_of = [&](int r) { return yper ? (r < 0 ? r + ny : (r >= ny ? r - ny : r)) : r; };
-  auto row_ok = [&](int r) { return yper || (r >= 0 && r < ny); };
-  prefetch_bulk(a, x, row_of(y0 - h), pre);
-  prefetch_bulk(a, x, row_of(y0 - h + 1), pre1);
+  int fr[S], lr[S];  // raw flag and link entries of rows r, r-1, ..., r-S+1
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    fr[j] = 0;
+    lr[j] = -1;
+  }
+  RowIn cur, nxt;
+  row_load(a, x, row_of(y0 - h), cur);
   bool bad[S];
 #pragma unroll
   for (int l = 0; l < S; ++l) bad[l] = false;
 #pragma unroll 1
   for (int r = y0 - h; r <= y1 + h - 1; ++r) {
-    float nxt[9];
-    prefetch_bulk(a, x, row_of(r + 2), nxt);
+    row_load(a, x, row_of(r + 1), nxt);
+#pragma unroll
+    for (int j = S - 1; j > 0; --j) {
+      fr[j] = fr[j - 1];
+      lr[j] = lr[j - 1];
+    }
+    fr[0] = cur.fl;
+    lr[0] = cur.li;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       lv[0][0][k] = lv[0][1][k];
       lv[0][1][k] = lv[0][2][k];
     }
-    // level 1 (f*(t+1)) of row r
-    first_update<COLL>(a, x, row_of(r), col_ok && row_ok(r), out_col && r >= y0 && r < y1, pre, lv[0][2], bad[0]);
+    {  // level 1 (f*(t+1)) of row r
+      float own[9];
+      own[0] = cur.pl[0];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      pre[k] = pre1[k];
-      pre1[k] = nxt[k];
+      for (int k = 1; k < 9; ++k) own[k] = cur.own[k - 1];
+      update_regs<COLL, true>(a, a.partial, x, row_of(r), col_ok && row_ok(r), out_col && r >= y0 && r < y1,
+                              cur.pl, own, own, own, fr[0], lr[0], rt, rb, lv[0][2], bad[0]);
     }
 #pragma unroll
     for (int l = 2; l <= S; ++l) {
       if (r < y0 - h + 2 * (l - 1)) continue;
       const int q = r - (l - 1);  // level l of row q
+      float c[9];
+      pull_rows(lv[l - 2][0], lv[l - 2][1], lv[l - 2][2], c);
       if (l < S) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
           lv[l - 1][0][k] = lv[l - 1][1][k];
           lv[l - 1][1][k] = lv[l - 1][2][k];
         }
-        second_update<COLL>(a, level_partial(a, l), x, row_of(q), col_ok && row_ok(q), out_col && q >= y0 && q < y1,
-                      lv[l - 2][0], lv[l - 2][1], lv[l - 2][2], lv[l - 1][2], bad[l - 1]);
+        update_regs<COLL, false>(a, level_partial(a, l), x, row_of(q), col_ok && row_ok(q),
+                                 out_col && q >= y0 && q < y1, c, lv[l - 2][0], lv[l - 2][1], lv[l - 2][2],
+                                 fr[l - 1], lr[l - 1], rt, rb, lv[l - 1][2], bad[l - 1]);
       } else {
         float out[9];
-        second_update<COLL>(a, level_partial(a, l), x, q, col_ok, out_col, lv[l - 2][0], lv[l - 2][1], lv[l - 2][2], out,
-                      bad[S - 1]);
+        update_regs<COLL, false>(a, level_partial(a, l), x, q, col_ok, out_col, c, lv[l - 2][0], lv[l - 2][1],
+                                 lv[l - 2][2], fr[l - 1], lr[l - 1], rt, rb, out, bad[S - 1]);
         if (out_col) store9<NT>(a.B, P, (uint32_t)q * Wp + (uint32_t)x, out);
       }
     }
+    cur = nxt;
   }
 #pragma unroll
   for (int l = 0; l < S; ++l) report_bad(a.bad, bad[l], a.slot + l);
+}
+
+// One launch, two steps.  The first blocks take the boundary sub-segments
+// (segments listed on the host, cut into SUB rows each so that they run
+// alongside the interior ones: 2 rows keep them short where the launch is
+// short, 4 halve their recomputed rows where it is long); the later blocks
+// one segment per wave, in
+// row-major order of (segment, strip), so that the waves in flight at any
+// time cover a narrow band of rows, four neighbouring strips per block.
+// (Orders that keep vertically adjacent segments on one XCD, so that their
+// shared rows are read once into its L2, fetch 30 % fewer bytes but ran
+// 4-10 % slower: the plain order's DRAM locality wins.)
+template <bool NT, int H, int SUB>
+__global__ __launch_bounds__(256) void step2_kernel(StepArgs a) {
+  constexpr int per = (H + SUB - 1) / SUB;
+  const int gen_blocks = (a.n_gen * per + 3) / 4;
+  const int b = (int)blockIdx.x, w = (int)(threadIdx.x >> 6);
+  if (b < gen_blocks) {
+    const int wave = b * 4 + w;
+    if (wave < a.n_gen * per) general_wave_n<NT, SUB, 2, kEither>(a, a.gen[wave / per], wave % per);
+    return;
+  }
+  const int wave = (b - gen_blocks) * 4 + w;
+  if (wave < a.t.ntx * a.t.nty) bulk_wave<NT, H>(a, wave % a.t.ntx, wave / a.t.ntx);
 }
 
 // One launch, S steps; blocks as in step2_kernel.

@@ -217,16 +217,17 @@ def _closure_run(kw, variant, interval, graphs, calls, seed=21):
 @pytest.mark.parametrize("interval", [1, 2, 8])
 def test_closure_interval_is_the_same_on_every_kernel_and_schedule(interval):
     """A closure evaluated every `interval` steps gives bit-identical results
-    with one or two steps per launch (a four-step variant falls back to
-    single steps while the closure is on), with or without graph replay, and
-    for any split of the steps into calls; with interval 1 every step is
-    evaluated."""
+    with one to four steps per launch (a launch takes several steps only
+    where no evaluation falls inside it: at interval 8 three-step variants mix
+    fused and single launches), with or without graph replay, and for any
+    split of the steps into calls; with interval 1 every step is evaluated."""
     kw = _trunc()
     by_name = {lbm.variant_name(v): v for v in range(1, lbm.num_variants() + 1)}
-    t2, t4 = by_name["t2_h4"], by_name["t4_h8_s8"]
+    t2, t3, t4 = by_name["t2_h4"], by_name["t3_h8_s2"], by_name["t4_h8_s8"]
     ref = _closure_run(kw, 1, interval, False, [131])
     for variant, graphs, calls in ((t2, False, [131]), (t2, True, [131]), (t2, True, [3, 64, 1, 63]),
-                                   (1, True, [70, 61]), (t4, True, [131]), (t4, False, [5, 126])):
+                                   (1, True, [70, 61]), (t4, True, [131]), (t4, False, [5, 126]),
+                                   (t3, True, [131]), (t3, False, [7, 124])):
         got = _closure_run(kw, variant, interval, graphs, calls)
         note(f"  interval {interval} variant {lbm.variant_name(variant)} graphs {graphs} calls {calls}")
         assert np.array_equal(got[0], ref[0])
