@@ -1377,17 +1377,16 @@ const Variant& variant(int v) { return kVariants[v - 1]; }
 // slab): below 2^20 nodes the lattice lives in the caches and one launch per
 // step, with cached stores and each XCD on its own band of rows, is fastest
 // (the deeper kernels' boundary waves set their launch time there).  From
-// 2^20 nodes fused steps win: at 1.4 M nodes four steps with 2-row boundary
-// pieces (98 k MLUPS against 88 k for two steps), at 2.8 M three steps with
-// 4-row pieces (147 k), at 5.5 M four steps with 4-row pieces (173 k), at
-// 22 M four steps with 8-row pieces (204 k; one step per launch: 82 k).
-// Longer boundary pieces recompute fewer rows but lengthen the serial chain
-// of each boundary wave, which only the longest launches hide.
+// 2^20 nodes fused steps win: at 1.4 M nodes three steps with 2-row boundary
+// pieces (119 k MLUPS against 111 k for two steps), at 2.8 M three steps
+// with 4-row pieces (149 k), from 5.5 M four steps with 8-row pieces (187 k;
+// 206 k at 22 M, where one step per launch gives 82 k).  Longer boundary
+// pieces recompute fewer rows but lengthen the serial chain of each boundary
+// wave, which only long launches hide.
 int default_variant(int64_t nodes) {
-  const char* want = nodes >= ((int64_t)1 << 24)   ? "t4_h8_s8"
-                     : nodes >= ((int64_t)1 << 22) ? "t4_h8_s4"
+  const char* want = nodes >= ((int64_t)1 << 22)   ? "t4_h8_s8"
                      : nodes >= ((int64_t)1 << 21) ? "t3_h8_s4"
-                     : nodes >= ((int64_t)1 << 20) ? "t4_h8_s2"
+                     : nodes >= ((int64_t)1 << 20) ? "t3_h8_s2"
                                                    : "v1_ty1_xcd";
   for (int v = 1; v <= num_variants(); ++v)
     if (std::strcmp(kVariants[v - 1].name, want) == 0) return v;
