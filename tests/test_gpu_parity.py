@@ -48,6 +48,33 @@ def test_channel_every_boundary_random_state(wall, outlet):
     assert np.abs(fx - ofx).max() < 1e-5 and np.abs(fy - ofy).max() < 1e-5
 
 
+@pytest.mark.parametrize("nx", [65, 128, 129, 40])
+@pytest.mark.parametrize("wall,outlet", [(lbm.WALL_MOVING_BB, lbm.OUTLET_COPY_ALL),
+                                         (lbm.WALL_FREE_SLIP, lbm.OUTLET_COPY_UNKNOWN)])
+def test_outlet_at_every_wave_lane_position(nx, wall, outlet):
+    """Channels whose outlet column falls on lane 0 of a wave (nx = 65, 129:
+    the one-step kernel's boundary waves then take the node-by-node path, as
+    the left neighbour the outlet copies is in the previous wave), on lane 63
+    (nx = 128) or in the inlet's wave (nx = 40), with a small cylinder, from a
+    disturbed state: against the oracle, then bit for bit across one-step
+    variants with one, two and four nodes per lane and two fused ones."""
+    kw = dict(nx=nx, ny=37, diameter=4, cx2=28, cy2=36, u_in=0.05, tau=0.62, wall=wall, outlet_mode=outlet)
+    seed = 300 + nx + wall
+    lat, o, (fx, fy, _, _), (ofx, ofy) = run_both(kw, 30, seed=seed)
+    solid = oracle.digitise(oracle.OracleParams(**_oracle_kwargs(kw)))
+    compare_state(lat, o, solid)
+    assert np.abs(fx - ofx).max() < 1e-5 and np.abs(fy - ofy).max() < 1e-5
+    by_name = {lbm.variant_name(v): v for v in range(1, lbm.num_variants() + 1)}
+    ref_f, ref_forces = _run_gpu(kw, 37, by_name["v1_ty1_nt"], seed)
+    for name in ("v1_ty1_xcd", "v2_ty1_nt", "v4_ty1_nt", "t2_h4", "t3_h8_s2"):
+        f, forces = _run_gpu(kw, 37, by_name[name], seed)
+        note(f"  variant {name}")
+        assert np.array_equal(f, ref_f), name
+        for a, b in zip(forces, ref_forces):
+            if a is not None:
+                assert np.array_equal(a, b), name
+
+
 @pytest.mark.parametrize("wall", ALL_WALLS)
 def test_uniform_flow_fixed_point(wall):
     kw = dict(nx=300, ny=70, u_in=0.08, tau=0.7, wall=wall, perturb_amp=0.0)
