@@ -674,24 +674,45 @@ __device__ __forceinline__ void update_regs(const StepArgs& a, double2* __restri
         bh[8] = from_right(w0[6]);
       }
     }
+    // Streamed values; a source outside the lattice exists only across an
+    // open edge (with the periodic modes the lanes and rows already hold the
+    // wrapped neighbours), and its population is one of the missing ones,
+    // set to zero for the corrections below.  Every test that picks the work
+    // is uniform across the wave: the row is the same for all lanes.
     float g[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      if (k > 0 && ((fl >> k) & 1) && !a.p.full_bb) {  // bounce-back on the cylinder
+    for (int k = 0; k < 9; ++k) g[k] = c[k];
+    if (open_x && __any(active && (x == 0 || x == nx - 1))) {
+      const bool w = x == 0, e = x == nx - 1;
+      g[1] = w ? 0.0f : g[1];
+      g[5] = w ? 0.0f : g[5];
+      g[8] = w ? 0.0f : g[8];
+      g[3] = e ? 0.0f : g[3];
+      g[6] = e ? 0.0f : g[6];
+      g[7] = e ? 0.0f : g[7];
+    }
+    const bool wall_row = a.p.wall != kWallPeriodic && (y == 0 || y == ny - 1);
+    if (wall_row) {
+      const bool s0 = y == 0;
+      g[2] = s0 ? 0.0f : g[2];
+      g[5] = s0 ? 0.0f : g[5];
+      g[6] = s0 ? 0.0f : g[6];
+      g[4] = s0 ? g[4] : 0.0f;
+      g[7] = s0 ? g[7] : 0.0f;
+      g[8] = s0 ? g[8] : 0.0f;
+    }
+    if (!a.p.full_bb && __any(fl >> 1)) {  // bounce-back on the cylinder
+#pragma unroll
+      for (int k = 1; k < 9; ++k) {
+        if (!((fl >> k) & 1)) continue;
         if (interp) {
           const float q = a.g.q[8 * li + k - 1];
           g[k] = bfl(q, w1[OPP[k]], bh[k], w1[k]);
         } else {
           g[k] = w1[OPP[k]];
         }
-        continue;
       }
-      int sx = x - CX[k], sy = y - CY[k];
-      if (a.p.x_periodic) sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
-      if (a.p.wall == kWallPeriodic) sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
-      g[k] = (sx >= 0 && sx < nx && sy >= 0 && sy < ny) ? c[k] : 0.0f;
     }
-    const bool wall_row = a.p.wall != kWallPeriodic && (y == 0 || y == ny - 1);
     const bool wall_x = a.p.x_periodic || (x >= 1 && x <= nx - 2);
     if (active && wall_row && wall_x) {
       wall_bc(a.p, y == ny - 1, w1, g);
