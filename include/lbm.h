@@ -195,9 +195,9 @@ lbm_status lbm_shedding_stats(const double* cd, const double* cl, int64_t n, dou
  * registers, so one launch reads and writes each population once for S node
  * updates; the steps left over (a remainder of n, or steps between learned-
  * closure evaluations that do not fill a launch) run the one-step kernel.
- * The default of a new context is "t4_h8_s8" from 2^22 nodes, "t3_h8_s4"
- * from 2^21, "t3_h8_s2" from 2^20 and the one-step "v1_ty1_xcd" (cached
- * stores, each XCD on its own band of rows) below ("_sN": segments that need
+ * The default of a new context is "t4_h8_s8" from 2^21 nodes, "t3_h8_s2"
+ * from 2^20 and the one-step "v1_ty1_xcd" (cached stores, each XCD on its
+ * own band of rows) below ("_sN": segments that need
  * the boundary code run in pieces of N rows).  lbm_get_variant
  * reports the variant in use. */
 int32_t lbm_num_variants(void);

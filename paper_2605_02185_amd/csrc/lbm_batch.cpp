@@ -230,8 +230,8 @@ void free_batch(lbm_batch* b) {
 
 // Four steps per launch with 8-row boundary pieces once the ensemble holds
 // 2^22 nodes: on the 64 cylinder channels of 55 k - 882 k nodes (26.3 M
-// together, MRT) 129 k MLUPS against 83 k for one step per launch and
-// 91-114 k for the other multi-step variants.  Smaller ensembles keep one
+// together, MRT) 152 k MLUPS against 83 k for one step per launch and
+// 116-137 k for the other multi-step variants.  Smaller ensembles keep one
 // step per launch, like the single lattices of their size.
 int batch_default_variant(const lbm_batch* b) {
   int64_t nodes = 0;

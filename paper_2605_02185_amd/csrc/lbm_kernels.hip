@@ -1399,14 +1399,13 @@ const Variant& variant(int v) { return kVariants[v - 1]; }
 // step, with cached stores and each XCD on its own band of rows, is fastest
 // (the deeper kernels' boundary waves set their launch time there).  From
 // 2^20 nodes fused steps win: at 1.4 M nodes three steps with 2-row boundary
-// pieces (119 k MLUPS against 111 k for two steps), at 2.8 M three steps
-// with 4-row pieces (149 k), from 5.5 M four steps with 8-row pieces (187 k;
-// 206 k at 22 M, where one step per launch gives 82 k).  Longer boundary
-// pieces recompute fewer rows but lengthen the serial chain of each boundary
-// wave, which only long launches hide.
+// pieces (145 k MLUPS against 134 k for four and 112 k for two steps), from
+// 2.8 M four steps with 8-row pieces (167 k on the 2.8 M slab, 191 k at
+// 5.5 M, 209 k at 22 M, where one step per launch gives 82 k).  Longer
+// boundary pieces recompute fewer rows but lengthen the serial chain of each
+// boundary wave, which only long launches hide.
 int default_variant(int64_t nodes) {
-  const char* want = nodes >= ((int64_t)1 << 22)   ? "t4_h8_s8"
-                     : nodes >= ((int64_t)1 << 21) ? "t3_h8_s4"
+  const char* want = nodes >= ((int64_t)1 << 21)   ? "t4_h8_s8"
                      : nodes >= ((int64_t)1 << 20) ? "t3_h8_s2"
                                                    : "v1_ty1_xcd";
   for (int v = 1; v <= num_variants(); ++v)
