@@ -196,9 +196,10 @@ lbm_status lbm_shedding_stats(const double* cd, const double* cl, int64_t n, dou
  * updates; the steps left over (a remainder of n, or steps between learned-
  * closure evaluations that do not fill a launch) run the one-step kernel.
  * The default of a new context is "t4_h8_s8" from 2^21 nodes, "t3_h8_s2"
- * from 2^20 and the one-step "v1_ty1_xcd" (cached stores, each XCD on its
- * own band of rows) below ("_sN": segments that need
- * the boundary code run in pieces of N rows).  lbm_get_variant
+ * from 2^20, "t2_h4_u1" from 2^18 and the one-step "v1_ty1_xcd" (cached
+ * stores, each XCD on its own band of rows) below ("_sN": segments that
+ * need the boundary code run in pieces of N rows; "_uN": pieces of N rows
+ * that load all their rows before any update).  lbm_get_variant
  * reports the variant in use. */
 int32_t lbm_num_variants(void);
 lbm_status lbm_set_variant(lbm_ctx* ctx, int32_t variant);

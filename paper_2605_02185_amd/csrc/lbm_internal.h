@@ -135,6 +135,7 @@ struct Variant {
   int remap_xcd, nontemporal;
   int steps;           // time steps per launch (1, or 2-4 with the intermediate states in registers)
   int sub;             // two-step: rows per wave of the segments that need the boundary code
+  int unrolled;        // 1: those waves issue every row's loads first, with no row loop
 };
 
 // Kernel launchers (lbm_kernels.hip).  All return the launch status.

@@ -1106,6 +1106,92 @@ __device__ __forceinline__ void general_wave_n(const StepArgs& a, int segment, i
   for (int l = 0; l < S; ++l) report_bad(a.bad, bad[l], a.slot + l);
 }
 
+// A boundary piece as in general_wave_n, with the loads of all its
+// SUB + 2(S - 1) first-level rows issued before any update and no row loop:
+// the piece's serial chain is one memory latency plus its updates, the
+// first-level rows independent of each other, which suits short launches
+// (lattices of a few hundred thousand nodes) at the cost of more registers
+// and code.  Rows past the end of a short piece are loaded (clamped) but
+// not worked on, as in the loop.
+template <bool NT, int SUB, int S, int COLL>
+__device__ __forceinline__ void general_wave_u(const StepArgs& a, int segment, int sub) {
+  constexpr int h = S - 1, W = 64 - 2 * h, N1 = SUB + 2 * h;
+  const int lane = (int)(threadIdx.x & 63);
+  const int St = a.t.ntx, H = a.t.tile_y;
+  const int strip = segment % St, seg = segment / St;
+  const int nx = a.g.nx, ny = a.g.ny;
+  const bool xper = a.p.x_periodic, yper = a.p.wall == kWallPeriodic;
+  const int xs = strip_start(a.g, a.t, xper, strip);
+  const int y0 = seg * H + sub * SUB;
+  if (y0 >= ny) return;
+  const int y1 = min(min(y0 + SUB, seg * H + H), ny);
+  const int ux = xs - h + lane;  // column before wrapping
+  const int x = xper ? ((ux % nx) + nx) % nx : ux;
+  const bool col_ok = xper || (ux >= 0 && ux < nx);
+  const bool out_col = lane >= h && lane < h + W && ux >= 0 && ux < nx;
+  const uint32_t P = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
+  auto row_of = [&](int r) { return yper ? (r < 0 ? r + ny : (r >= ny ? r - ny : r)) : r; };
+  auto row_ok = [&](int r) { return yper || (r >= 0 && r < ny); };
+  RowIn in[N1];
+#pragma unroll
+  for (int i = 0; i < N1; ++i) row_load(a, x, row_of(y0 - h + i), in[i]);
+  float rt[3], rb[3];
+  closure_rows_load(a, y0 - h <= 0 || y1 + h - 1 >= ny - 1, x, rt, rb);
+  float lv[S - 1][3][9];
+#pragma unroll
+  for (int l = 0; l < S - 1; ++l)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) lv[l][j][k] = 0.0f;
+  bool bad[S];
+#pragma unroll
+  for (int l = 0; l < S; ++l) bad[l] = false;
+#pragma unroll
+  for (int i = 0; i < N1; ++i) {
+    const int r = y0 - h + i;
+    if (r > y1 + h - 1) break;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      lv[0][0][k] = lv[0][1][k];
+      lv[0][1][k] = lv[0][2][k];
+    }
+    {  // level 1 (f*(t+1)) of row r
+      float own[9];
+      own[0] = in[i].pl[0];
+#pragma unroll
+      for (int k = 1; k < 9; ++k) own[k] = in[i].own[k - 1];
+      update_regs<COLL, true>(a, a.partial, x, row_of(r), col_ok && row_ok(r), out_col && r >= y0 && r < y1,
+                              in[i].pl, own, own, own, in[i].fl, in[i].li, rt, rb, lv[0][2], bad[0]);
+    }
+#pragma unroll
+    for (int l = 2; l <= S; ++l) {
+      if (i < 2 * (l - 1)) continue;
+      const int q = r - (l - 1);  // level l of row q
+      const RowIn& iq = in[i - (l - 1)];
+      float c[9];
+      pull_rows(lv[l - 2][0], lv[l - 2][1], lv[l - 2][2], c);
+      if (l < S) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          lv[l - 1][0][k] = lv[l - 1][1][k];
+          lv[l - 1][1][k] = lv[l - 1][2][k];
+        }
+        update_regs<COLL, false>(a, level_partial(a, l), x, row_of(q), col_ok && row_ok(q),
+                                 out_col && q >= y0 && q < y1, c, lv[l - 2][0], lv[l - 2][1], lv[l - 2][2], iq.fl,
+                                 iq.li, rt, rb, lv[l - 1][2], bad[l - 1]);
+      } else {
+        float out[9];
+        update_regs<COLL, false>(a, level_partial(a, l), x, q, col_ok, out_col, c, lv[l - 2][0], lv[l - 2][1],
+                                 lv[l - 2][2], iq.fl, iq.li, rt, rb, out, bad[S - 1]);
+        if (out_col) store9<NT>(a.B, P, (uint32_t)q * Wp + (uint32_t)x, out);
+      }
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < S; ++l) report_bad(a.bad, bad[l], a.slot + l);
+}
+
 // One launch, two steps.  The first blocks take the boundary sub-segments
 // (segments listed on the host, cut into SUB rows each so that they run
 // alongside the interior ones: 2 rows keep them short where the launch is
@@ -1116,14 +1202,19 @@ __device__ __forceinline__ void general_wave_n(const StepArgs& a, int segment, i
 // (Orders that keep vertically adjacent segments on one XCD, so that their
 // shared rows are read once into its L2, fetch 30 % fewer bytes but ran
 // 4-10 % slower: the plain order's DRAM locality wins.)
-template <bool NT, int H, int SUB>
+template <bool NT, int H, int SUB, bool UNR>
 __global__ __launch_bounds__(256) void step2_kernel(StepArgs a) {
   constexpr int per = (H + SUB - 1) / SUB;
   const int gen_blocks = (a.n_gen * per + 3) / 4;
   const int b = (int)blockIdx.x, w = (int)(threadIdx.x >> 6);
   if (b < gen_blocks) {
     const int wave = b * 4 + w;
-    if (wave < a.n_gen * per) general_wave_n<NT, SUB, 2, kEither>(a, a.gen[wave / per], wave % per);
+    if (wave < a.n_gen * per) {
+      if constexpr (UNR)
+        general_wave_u<NT, SUB, 2, kEither>(a, a.gen[wave / per], wave % per);
+      else
+        general_wave_n<NT, SUB, 2, kEither>(a, a.gen[wave / per], wave % per);
+    }
     return;
   }
   const int wave = (b - gen_blocks) * 4 + w;
@@ -1387,6 +1478,7 @@ constexpr Variant kVariants[] = {
     {"t4_h12_s12", kStrip4, 12, 1, 0, 0, 4, 12},
     {"t3_h8_s2", kStrip3, 8, 1, 0, 0, 3, 2},
     {"t4_h8_s2", kStrip4, 8, 1, 0, 0, 4, 2},
+    {"t2_h4_u1", kStrip2, 4, 1, 0, 0, 2, 1, 1},
 };
 
 }  // namespace
@@ -1395,10 +1487,13 @@ int num_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 const Variant& variant(int v) { return kVariants[v - 1]; }
 
 // Measured on the MI355X (BGK, D2Q9 cylinder channels and one x-periodic
-// slab): below 2^20 nodes the lattice lives in the caches and one launch per
-// step, with cached stores and each XCD on its own band of rows, is fastest
-// (the deeper kernels' boundary waves set their launch time there).  From
-// 2^20 nodes fused steps win: at 1.4 M nodes three steps with 2-row boundary
+// slab; MRT on the paper's lattice and the closure window): below 2^18 nodes
+// one launch per step, with cached stores and each XCD on its own band of
+// rows, is fastest (4.2 us per step at 86 k nodes against 4.7 us for two
+// steps); from 2^18 two steps with one-row boundary pieces that load all
+// their rows first (6.1 against 6.3 us per step at 320 k nodes, 6.3 against
+// 7.1 us at 458 k), where the deeper kernels' boundary chains still set the
+// launch time.  From 2^20 nodes more fused steps win: at 1.4 M nodes three steps with 2-row boundary
 // pieces (145 k MLUPS against 134 k for four and 112 k for two steps), from
 // 2.8 M four steps with 8-row pieces (167 k on the 2.8 M slab, 191 k at
 // 5.5 M, 209 k at 22 M, where one step per launch gives 82 k).  Longer
@@ -1407,6 +1502,7 @@ const Variant& variant(int v) { return kVariants[v - 1]; }
 int default_variant(int64_t nodes) {
   const char* want = nodes >= ((int64_t)1 << 21)   ? "t4_h8_s8"
                      : nodes >= ((int64_t)1 << 20) ? "t3_h8_s2"
+                     : nodes >= ((int64_t)1 << 18) ? "t2_h4_u1"
                                                    : "v1_ty1_xcd";
   for (int v = 1; v <= num_variants(); ++v)
     if (std::strcmp(kVariants[v - 1].name, want) == 0) return v;
@@ -1477,18 +1573,19 @@ hipError_t launch_step(const StepArgs& a, int v, hipStream_t s) {
     const int per = (var.tile_y + var.sub - 1) / var.sub;
     const int blocks = (a.n_gen * per + 3) / 4 + (a.t.ntx * a.t.nty + 3) / 4;
     const dim3 grid((unsigned)blocks), block(256);
-#define LBM_T2(NT, H, SUB)                                                 \
-  if (var.nontemporal == NT && var.tile_y == H && var.sub == SUB) {        \
-    hipLaunchKernelGGL((step2_kernel<NT, H, SUB>), grid, block, 0, s, a);  \
-    return hipGetLastError();                                              \
+#define LBM_T2(NT, H, SUB, UNR)                                                              \
+  if (var.nontemporal == NT && var.tile_y == H && var.sub == SUB && var.unrolled == UNR) {   \
+    hipLaunchKernelGGL((step2_kernel<NT, H, SUB, UNR>), grid, block, 0, s, a);               \
+    return hipGetLastError();                                                                \
   }
-    LBM_T2(false, 4, 2)
-    LBM_T2(false, 6, 2)
-    LBM_T2(false, 8, 2)
-    LBM_T2(true, 8, 2)
-    LBM_T2(false, 16, 2)
-    LBM_T2(false, 4, 4)
-    LBM_T2(false, 6, 4)
+    LBM_T2(false, 4, 2, 0)
+    LBM_T2(false, 6, 2, 0)
+    LBM_T2(false, 8, 2, 0)
+    LBM_T2(true, 8, 2, 0)
+    LBM_T2(false, 16, 2, 0)
+    LBM_T2(false, 4, 4, 0)
+    LBM_T2(false, 6, 4, 0)
+    LBM_T2(false, 4, 1, 1)
 #undef LBM_T2
     return hipErrorInvalidValue;
   }

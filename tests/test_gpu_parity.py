@@ -291,14 +291,16 @@ def test_two_step_variants_match_one_step_bitwise(case):
 
 
 def test_default_variant_follows_the_lattice_size():
-    """One step per launch below 2^20 nodes (cached stores, XCD bands), three
-    from 2^20 (2-row boundary pieces), four from 2^21 (8-row pieces); variant
-    0 restores the default."""
+    """One step per launch below 2^18 nodes (cached stores, XCD bands), two
+    from 2^18 (one-row boundary pieces loading all their rows first), three
+    from 2^20 (2-row pieces), four from 2^21 (8-row pieces); variant 0
+    restores the default."""
     small = lbm.Lattice(lbm.make_params(**WORKLOADS["cyl_d10"]))
     big = lbm.Lattice(lbm.make_params(**WORKLOADS["cyl_d40"]))
     assert lbm.variant_name(small.variant) == "v1_ty1_xcd"
     assert lbm.variant_name(big.variant) == "t3_h8_s2"
-    for name, want in (("slab_d160_of8", "t4_h8_s8"), ("cyl_d80", "t4_h8_s8"), ("cyl_d160", "t4_h8_s8")):
+    for name, want in (("cyl_d20_mrt", "t2_h4_u1"), ("slab_d160_of8", "t4_h8_s8"), ("cyl_d80", "t4_h8_s8"),
+                       ("cyl_d160", "t4_h8_s8")):
         lat = lbm.Lattice(lbm.make_params(**WORKLOADS[name]))
         assert lbm.variant_name(lat.variant) == want, name
         lat.close()
