@@ -7,9 +7,11 @@ known size, run in the same process: FETCH_SIZE and WRITE_SIZE count in
 units that differ from bytes by a fixed factor on this chip.
 
     python bench_traffic.py FETCH_CSV WRITE_CSV --variant t2_h4 [--workload cyl_d160] [--collision bgk]
-                            [--valu VALU_CSV]
+                            [--valu VALU_CSV] [--out PATH]
 
 The variant is the one bench.py reports in config.variant for the same run.
+The summary goes to the file bench.py reads (profiles/traffic_step_kernel.json)
+unless --out names another (for workloads other than the default one).
 With --valu, a third run's counters (SQ_INSTS_VALU, SQ_INSTS_VALU_FMA_F32,
 SQ_INSTS_VALU_ADD_F32, SQ_INSTS_VALU_MUL_F32, SQ_INSTS_VALU_TRANS_F32,
 SQ_ACTIVE_INST_VALU, GRBM_GUI_ACTIVE) add the vector-ALU side: FP32
@@ -43,6 +45,7 @@ def main():
     ap.add_argument("--collision", default="bgk")
     ap.add_argument("--variant", required=True)
     ap.add_argument("--valu", help="counter_collection.csv of the VALU counter run")
+    ap.add_argument("--out", default=bench.TRAFFIC_FILE, help="where to write the summary")
     a = ap.parse_args()
     steps = {"t2": 2, "t3": 3, "t4": 4}.get(a.variant[:2], 1)
     kname = {1: "step_kernel<", 2: "step2_kernel"}.get(steps, "multistep_kernel")
@@ -102,7 +105,7 @@ def main():
             "valu_insts_per_update": round(64 * c["SQ_INSTS_VALU"] / (nodes * steps), 1),
             "valu_busy_pct": round(100 * c["SQ_ACTIVE_INST_VALU"] / cus / (c["GRBM_GUI_ACTIVE"] / xcc), 1),
         }
-    with open(bench.TRAFFIC_FILE, "w") as fh:
+    with open(a.out, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
 
