@@ -3,22 +3,33 @@
 One step = one pass of the whole hot path over the lattice: pull streaming,
 half-way bounce-back on the cylinder, wall/outlet/inlet corrections, the
 collision (BGK by default) and the FP64 momentum-exchange force (plus its
-fixed-order history reduction every 64 steps).  The default workload is the
+fixed-order history reduction every 96 steps).  The default workload is the
 D = 160 cylinder channel (6560 x 3360 = 22.0 M nodes, Re = 100, U = 0.05,
 free-slip walls), whose two population buffers (1.6 GB) are far larger than
 the 256 MB Infinity Cache.  At this size the library's default kernel takes
-two steps per launch with the intermediate populations in registers.
+four steps per launch with the intermediate populations in registers.
 
 Prints one JSON line:
   value      MLUPS = nx * ny * steps / time / 1e6 (all nodes)
-  roofline   algorithmic bytes (72 B per node update: 9 FP32 loads + 9 FP32
-             stores) times the node updates of the timed region, over its
-             duration, against the 8 TB/s HBM3E peak; `traffic` is the HBM
-             bytes per launch from the committed rocprofv3 FETCH_SIZE /
-             WRITE_SIZE summary when it was taken on the current kernel
-             source and configuration (else null), and `hbm_GBs` the
-             bandwidth that traffic implies at the measured launch rate
-  cpu_baseline  the FP64 oracle timed on this host on a bounded sample
+  roofline   for the dominant kernel, per launch (S steps):
+             achieved  HBM bytes the rocprofv3 FETCH_SIZE / WRITE_SIZE
+                       counters give per launch (`traffic`, scaled by what
+                       they read for a copy of known size) over the live
+                       launch time, against the 8 TB/s HBM3E peak (`frac`);
+                       only while the committed counter summary was taken on
+                       the current kernel source and configuration
+             frac_of_floor  one read and one write of the state (72 B per
+                       node: the least an S-step launch can move) over the
+                       launch time, against the peak
+             effective_GBs  72 B per node update times the updates (the
+                       per-update accounting of the LBM literature; passes
+                       the peak once several steps share one pass)
+             valu      the vector-ALU side from the same counter summary
+  cpu_baseline  the FP64 oracle, built with gcc -O3 -march=native on this
+             host, timed on a bounded sample of the same lattice; samples of
+             the other lattices at 1 and all threads
+  ensemble   the 64-case ensemble against 64 separate lattices
+  closure    the learned boundary closure against the full domain
 """
 from __future__ import annotations
 
@@ -75,28 +86,73 @@ def copy_ceiling(torch, lbm, nbytes: int, reps: int = 20) -> float:
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(w: dict, budget_s: float) -> dict:
-    """The FP64 oracle, as it stands, on this host: steps of the same lattice
-    until about budget_s seconds of stepping have elapsed."""
-    import oracle
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
 
-    o = oracle.Oracle(oracle.OracleParams(**w))
+    return platform.processor() or "unknown"
+
+
+def _time_oracle(oracle, lib, w: dict, threads: int, max_steps: int, budget_s: float) -> dict:
+    """Steps of one lattice on `threads` threads until max_steps or about
+    budget_s seconds of stepping (set-up and the first step not timed)."""
+    oracle.set_threads(threads, lib)
+    o = oracle.Oracle(oracle.OracleParams(**w), lib_path=lib)
     o.step(1)  # first touch of the buffers
     steps, t0 = 0, time.perf_counter()
-    while True:
+    while steps < max_steps:
         o.step(1)
         steps += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 200:
+        if el >= budget_s:
             break
-    nodes = w["nx"] * w["ny"]
+    el = time.perf_counter() - t0
     o.close()
+    nodes = w["nx"] * w["ny"]
+    return {"lattice": f"{w['nx']}x{w['ny']}", "threads": threads, "steps": steps, "seconds": round(el, 2),
+            "mlups": round(nodes * steps / el / 1e6, 2)}
+
+
+def cpu_baseline(w: dict, budget_s: float) -> dict:
+    """The FP64 oracle (its C source as it stands), compiled here with gcc
+    -O3 -march=native and timed on this host: the benchmark's lattice on all
+    the threads OpenMP is given (about 40 % of budget_s), then the D = 10,
+    40 and 80 channels for up to 2000, 1000 and 200 steps on one thread and
+    on all of them (the rest of the budget, split evenly)."""
+    import tempfile
+
+    import oracle
+    from lbm_inputs import WORKLOADS
+
+    lib = os.path.join(tempfile.gettempdir(), f"liblbm_oracle_native_{os.getpid()}.so")
+    oracle.build_native(lib)
+    try:
+        nthreads = oracle.threads(lib)
+        head = _time_oracle(oracle, lib, w, nthreads, 200, 0.4 * budget_s)
+        samples = []
+        per = 0.6 * budget_s / 6
+        for name, steps in (("cyl_d10", 2000), ("cyl_d40", 1000), ("cyl_d80", 200)):
+            for th in (1, nthreads):
+                samples.append(dict(_time_oracle(oracle, lib, WORKLOADS[name], th, steps, per), workload=name))
+        oracle.set_threads(nthreads, lib)
+    finally:
+        os.remove(lib)
     return {
-        "value": nodes * steps / el / 1e6,
+        "value": head["mlups"],
         "unit": "MLUPS",
-        "cores": oracle.threads(),
+        "cores": nthreads,
         "kind": "oracle",
-        "sample": f"{steps} steps of the {w['nx']}x{w['ny']} lattice ({el:.1f} s, FP64, OpenMP)",
+        "sample": f"{head['steps']} steps of the {head['lattice']} lattice ({head['seconds']} s, FP64, "
+                  f"{nthreads} OpenMP threads)",
+        "cpu_model": cpu_model(),
+        "build": "gcc " + " ".join(oracle.NATIVE_FLAGS),
+        "bytes_per_update": 144,
+        "samples": samples,
     }
 
 
@@ -110,13 +166,13 @@ def main():
     ap.add_argument("--collision", choices=("bgk", "mrt"), default="bgk",
                     help="collision operator: BGK (Eq. 2) or MRT with the rates of Sec. 2.1 (Eq. 6)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-ceiling reference")
     ap.add_argument("--no-graphs", action="store_true", help="plain launches instead of graph replay")
-    ap.add_argument("--ensemble", action="store_true",
-                    help="also time the 64-case ensemble (MRT, tau from Re) against 64 separate lattices")
-    ap.add_argument("--closure", action="store_true",
-                    help="also train and evaluate the learned boundary closure (about a minute)")
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="skip the 64-case ensemble (MRT, tau from Re) against 64 separate lattices")
+    ap.add_argument("--no-closure", action="store_true",
+                    help="skip training and evaluating the learned boundary closure (about a minute)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -162,28 +218,42 @@ def main():
 
     vname = lbm.variant_name(lat.variant)
     steps_per_launch = {"t2": 2, "t3": 3, "t4": 4}.get(vname[:2], 1)
-    launch_ms = ms_per_step * steps_per_launch
-    achieved = BYTES_PER_NODE * nodes * steps_per_launch / (launch_ms * 1e-3) / 1e9
+    launch_s = ms_per_step * steps_per_launch * 1e-3
+    floor_bytes = BYTES_PER_NODE * nodes  # one read and one write of the state per launch
+    effective = BYTES_PER_NODE * nodes * steps_per_launch / launch_s / 1e9
+    floor_rate = floor_bytes / launch_s / 1e9
     counters = stored_counters(args.workload, args.collision, vname)
     traffic = counters.get("bytes_per_launch") if counters else None
     valu = counters.get("valu") if counters else None
+    achieved = traffic / launch_s / 1e9 if traffic else None
     roof = {
         "bound": "hbm",
-        "achieved": round(achieved, 1),
+        "achieved": round(achieved, 1) if achieved else None,
         "peak": PEAK_HBM_GBS,
         "unit": "GB/s",
-        "frac": round(achieved / PEAK_HBM_GBS, 4),
+        "frac": round(achieved / PEAK_HBM_GBS, 4) if achieved else None,
         "traffic": traffic,
         "kernel": {1: "step_kernel", 2: "step2_kernel"}.get(steps_per_launch, "multistep_kernel"),
         "steps_per_launch": steps_per_launch,
-        "launch_us": round(launch_ms * 1e3, 2),
-        "algorithmic_bytes_per_launch": BYTES_PER_NODE * nodes * steps_per_launch,
-        "hbm_GBs": round(traffic / (launch_ms * 1e-3) / 1e9, 1) if traffic else None,
+        "launch_us": round(launch_s * 1e6, 2),
+        "floor_bytes_per_launch": floor_bytes,
+        "frac_of_floor": round(floor_rate / PEAK_HBM_GBS, 4),
+        "traffic_over_floor": round(traffic / floor_bytes, 4) if traffic else None,
+        "effective_GBs": round(effective, 1),
+        "counters": ("profiles/traffic_step_kernel.json (kernel source " + counters["kernel_sha256_16"] + ")"
+                     if counters else "stale: taken on another kernel source or configuration"),
     }
     if valu:
-        # the vector ALU side of the same kernel, from the stored counters
-        roof["valu_busy_pct"] = valu["valu_busy_pct"]
-        roof["fp32_TFLOPs"] = round(valu["fp32_flop_per_launch"] / (launch_ms * 1e-3) / 1e12, 2)
+        # the vector ALU side of the same kernel, from the stored counters:
+        # FP32 operations per launch over the live launch time, against the
+        # 78.6 TFLOP/s of unpacked FP32 FMAs (256 CUs x 4 SIMDs x 16 lanes x
+        # 2 x 2.4 GHz; the packed forms behind the 157.3 figure are not used)
+        flops = valu["fp32_flop_per_launch"] / launch_s / 1e12
+        roof["valu"] = {"busy_pct": valu["valu_busy_pct"], "fp32_TFLOPs": round(flops, 2),
+                        "fp32_peak_TFLOPs": 78.6, "frac": round(flops / 78.6, 4),
+                        "insts_per_update": valu["valu_insts_per_update"]}
+    walls = {lbm.WALL_FREE_SLIP: "free-slip", lbm.WALL_PERIODIC: "periodic", lbm.WALL_NEBB: "nebb",
+             lbm.WALL_MOVING_BB: "moving-bb"}
     out = {
         "metric": "D2Q9 MLUPS & % HBM roofline",
         "value": round(mlups, 1),
@@ -200,8 +270,10 @@ def main():
         "config": {
             "workload": args.workload,
             "nx": w["nx"], "ny": w["ny"], "diameter": w.get("diameter", 0), "u_in": w["u_in"],
-            "re": w.get("re"), "tau": round(lbm.tau_of(p), 6), "wall": "free-slip",
-            "outlet": "x-periodic" if w.get("x_periodic") else "copy-all", "collision": args.collision,
+            "re": w.get("re"), "tau": round(lbm.tau_of(p), 6), "wall": walls[p.wall],
+            "outlet": ("x-periodic" if p.x_periodic else
+                       "copy-all" if p.outlet_mode == lbm.OUTLET_COPY_ALL else "copy-unknown"),
+            "collision": args.collision,
             "variant": vname,
             "graphs": not args.no_graphs,
         },
@@ -211,51 +283,69 @@ def main():
     }
     if not args.no_copy:
         cc = copy_ceiling(torch, lbm, 9 * nodes * 4)
-        out["copy_ceiling"] = {"GB/s": round(cc, 1), "frac_of_copy": round(achieved / cc, 4)}
+        out["copy_ceiling"] = {"GB/s": round(cc, 1),
+                               "frac_of_copy": round(achieved / cc, 4) if achieved else None}
     lat.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
-    if args.ensemble:
+    if not args.no_ensemble:
         out["ensemble"] = ensemble_result(torch, lbm)
-    if args.closure:
+    if not args.no_closure:
         out["closure"] = closure_result()
     print(json.dumps(out), flush=True)
 
 
-def ensemble_result(torch, lbm, steps: int = 1280) -> dict:
+def ensemble_result(torch, lbm, steps: int = 1920) -> dict:
     """The 64 cylinder channels (D 8..32, Re 60..200, U = 0.05, tau from Re,
-    MRT with the rates of Sec. 2.1): one Ensemble (its default variant)
-    against the same cases as 64 separate lattices stepped one after the
-    other, both after 128 warm-up steps; MLUPS over all nodes of all cases."""
+    MRT with the rates of Sec. 2.1): one Ensemble (the variant its autotuner
+    picks) against the same cases as 64 separate lattices (each on its own
+    default), both after 192 warm-up steps, timed with HIP events on the
+    stream they run on.  Per-case MLUPS: a case's node updates over the
+    ensemble's time (all cases advance together), and over the case's own
+    time when run alone."""
     from lbm_inputs import ensemble
 
     cases = ensemble(mrt=True)
-    nodes = sum(c["nx"] * c["ny"] for c in cases)
-    ens = lbm.Ensemble([lbm.make_params(**c) for c in cases])
+    sizes = [c["nx"] * c["ny"] for c in cases]
+    nodes = sum(sizes)
+    stream = torch.cuda.current_stream()
+
+    def timed(run):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3
+
+    t0 = time.perf_counter()
+    ens = lbm.Ensemble([lbm.make_params(**c) for c in cases], stream=stream.cuda_stream)
+    tune_s = time.perf_counter() - t0
     vname = lbm.variant_name(ens.variant)
-    ens.step(128)
+    ens.step(192)
     ens.sync()
-    t0 = time.perf_counter()
-    ens.step(steps)
+    t_ens = timed(lambda: ens.step(steps))
     ens.sync()
-    t_ens = time.perf_counter() - t0
     ens.close()
-    lats = [lbm.Lattice(lbm.make_params(**c)) for c in cases]
-    for lat in lats:
-        lat.step(128)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for lat in lats:
-        lat.step(steps)
-    for lat in lats:
+    t_alone = []
+    for c in cases:
+        lat = lbm.Lattice(lbm.make_params(**c), stream=stream.cuda_stream)
+        lat.step(192)
+        t_alone.append(timed(lambda: lat.step(steps)))
         lat.sync()
-    t_sep = time.perf_counter() - t0
-    for lat in lats:
         lat.close()
+    t_sep = sum(t_alone)
+    per_case = [round(n * steps / t_ens / 1e6, 1) for n in sizes]
+    per_alone = [round(n * steps / t / 1e6, 1) for n, t in zip(sizes, t_alone)]
     return {"cases": len(cases), "nodes": nodes, "steps": steps, "variant": vname,
+            "autotune_s": round(tune_s, 2),
             "mlups": round(nodes * steps / t_ens / 1e6, 1),
             "separate_mlups": round(nodes * steps / t_sep / 1e6, 1),
-            "speedup": round(t_sep / t_ens, 3)}
+            "speedup": round(t_sep / t_ens, 3),
+            "case_D": [c["diameter"] for c in cases],
+            "per_case_mlups": per_case,
+            "per_case_alone_mlups": per_alone}
 
 
 def closure_result() -> dict:

@@ -237,10 +237,12 @@ typedef struct lbm_batch lbm_batch;
 
 /* `cases[n]` as for lbm_create; `budgets` (may be NULL = unlimited) gives the
  * number of steps after which each case stops (retires) while the others go
- * on.  `tune_cache` (may be NULL) enables the autotuner with that cache file;
- * without it the default kernel variant is used: "t4_h8_s8" (four steps per
- * launch) when the cases hold 2^22 nodes or more together, else the one-step
- * "v1_ty1_nt". */
+ * on.  The kernel variant (tile shape, nodes per lane, steps per launch) is
+ * chosen by the autotuner: every variant lbm_batch_set_variant accepts is
+ * timed over 48 steps on a scratch ensemble of the same cases (allocated and
+ * freed inside this call) and the fastest is kept; lbm_batch_variant reports
+ * it.  `tune_cache` (may be NULL) names a text file of "key variant" lines:
+ * a hit skips the timing, a miss appends the choice. */
 lbm_status lbm_batch_create(const lbm_params* cases, const int64_t* budgets, int32_t n, void* stream,
                             const char* tune_cache, lbm_batch** out);
 void lbm_batch_destroy(lbm_batch* b);
@@ -261,6 +263,12 @@ lbm_status lbm_batch_forces(lbm_batch* b, int32_t c, int64_t first, int64_t coun
                             double* cd, double* cl);
 lbm_status lbm_batch_fields(lbm_batch* b, int32_t c, float* rho, float* ux, float* uy, int on_device);
 lbm_status lbm_batch_get_populations(lbm_batch* b, int32_t c, void* buf, int dtype, int on_device);
+
+/* As lbm_set_populations, for case `c`: the case's next step streams the
+ * given post-collision populations ([9][ny][nx] of that case, float32 or
+ * float64 as dtype, host or device memory).  Its step counter and force
+ * history are kept; the other cases are untouched. */
+lbm_status lbm_batch_set_populations(lbm_batch* b, int32_t c, const void* buf, int dtype, int on_device);
 
 /* Kernel variant in use (1-based, as lbm_variant_name). */
 int32_t lbm_batch_variant(const lbm_batch* b);

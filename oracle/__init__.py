@@ -40,6 +40,20 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+NATIVE_FLAGS = ["-O3", "-march=native", "-fopenmp"]
+
+
+def build_native(path: str) -> str:
+    """A second build of the same source for timing on the machine it runs
+    on (gcc -O3 -march=native, OpenMP), written to `path`.  The tests use
+    the portable -O2 build; this one is compiled where it is timed, so that
+    -march=native names that machine's CPU."""
+    tmp = path + ".tmp"
+    subprocess.check_call(["gcc", *NATIVE_FLAGS, "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, path)
+    return path
+
+
 class _Params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int),
@@ -65,16 +79,16 @@ class _Params(ctypes.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB_PATH):
+def _load(path: str | None = None):
+    path = path or _LIB_PATH
+    if path in _libs:
+        return _libs[path]
+    if path == _LIB_PATH and not os.path.exists(_LIB_PATH):
         build(force=False)
-    lib = ctypes.CDLL(_LIB_PATH)
+    lib = ctypes.CDLL(path)
     P = ctypes.POINTER(_Params)
     dp = ctypes.POINTER(ctypes.c_double)
     u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -93,11 +107,12 @@ def _load():
     lib.oracle_tau.argtypes = [P]
     lib.oracle_tau.restype = ctypes.c_double
     lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_mrt_matrix.argtypes = [dp]
     lib.oracle_links.restype = ctypes.c_long
     lib.oracle_links.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.oracle_mrt_meq.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
-    _lib = lib
+    _libs[path] = lib
     return lib
 
 
@@ -164,9 +179,14 @@ def mrt_meq(rho, ux, uy) -> np.ndarray:
     return out
 
 
-def threads() -> int:
+def threads(lib_path: str | None = None) -> int:
     """OpenMP threads used by the oracle's parallel loops."""
-    return _load().oracle_threads()
+    return _load(lib_path).oracle_threads()
+
+
+def set_threads(n: int, lib_path: str | None = None):
+    """Threads of the oracle's parallel loops from now on (timing only)."""
+    _load(lib_path).oracle_set_threads(n)
 
 
 def tau_of(p: OracleParams) -> float:
@@ -178,9 +198,10 @@ def tau_of(p: OracleParams) -> float:
 class Oracle:
     """Plain FP64 D2Q9 solver; state f[y][x][k] lives in C memory."""
 
-    def __init__(self, p: OracleParams, solid: np.ndarray | None = None):
+    def __init__(self, p: OracleParams, solid: np.ndarray | None = None, lib_path: str | None = None):
+        """`lib_path` selects another build of lbm_oracle.c (build_native)."""
         self.p = p
-        self._lib = _load()
+        self._lib = _load(lib_path)
         self._cp = p._c()
         sp = None
         if solid is not None:

@@ -625,3 +625,8 @@ void oracle_set_fstar(oracle* o, const double* in) {
 }
 
 int oracle_threads(void) { return omp_get_max_threads(); }
+
+/* Threads of the parallel loops that follow (n >= 1); timing only. */
+void oracle_set_threads(int n) {
+  if (n >= 1) omp_set_num_threads(n);
+}

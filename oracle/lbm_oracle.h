@@ -111,6 +111,7 @@ long oracle_links(const oracle* o, long* out_node, int* out_dir, double* out_q);
 
 /* OpenMP threads the oracle's parallel loops use. */
 int oracle_threads(void);
+void oracle_set_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -68,6 +68,11 @@ def shedding_stats(cd, cl, d, u, periods=5):
 
 def copy_probe(dst, src, nbytes: int, stream=None):
     """Plain streaming copy of nbytes between two device tensors (bandwidth reference)."""
+    for t, name in ((dst, "dst"), (src, "src")):
+        if not getattr(t, "is_cuda", False) or not t.is_contiguous():
+            raise LbmError(f"{name} must be a contiguous GPU tensor")
+        if t.numel() * t.element_size() < nbytes:
+            raise LbmError(f"{name} holds fewer than {nbytes} bytes")
     check(_lib.lib.lbm_copy_probe(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
                                   nbytes, _stream_handle(stream)))
 
@@ -78,6 +83,21 @@ def num_variants() -> int:
 
 def variant_name(v: int) -> str:
     return _lib.lib.lbm_variant_name(v).decode()
+
+
+def _device_ptr(t, numel: int, dtypes=("torch.float32",), name: str = "tensor") -> ctypes.c_void_p:
+    """The device address of a contiguous GPU tensor holding exactly `numel`
+    elements of one of `dtypes`; raises instead of letting a kernel read or
+    write past it."""
+    if not getattr(t, "is_cuda", False):
+        raise LbmError(f"{name} must be a GPU tensor")
+    if str(t.dtype) not in dtypes:
+        raise LbmError(f"{name} has dtype {t.dtype}; expected one of {', '.join(dtypes)}")
+    if not t.is_contiguous():
+        raise LbmError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise LbmError(f"{name} holds {t.numel()} elements; expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _stream_handle(stream):
@@ -149,14 +169,17 @@ class Lattice:
         """Training samples of a wnx x wny window at (ox, oy); nodes (int32),
         feat [n][36] and target [n][3] are device tensors."""
         n = nodes.numel()
-        check(_lib.lib.lbm_sample_boundary(self._h, ox, oy, wnx, wny, ctypes.c_void_p(nodes.data_ptr()), n,
-                                           ctypes.c_void_p(feat.data_ptr()), ctypes.c_void_p(target.data_ptr())))
+        pn = _device_ptr(nodes, n, ("torch.int32",), "nodes")
+        pf = _device_ptr(feat, 36 * n, name="feat")
+        pt = _device_ptr(target, 3 * n, name="target")
+        check(_lib.lib.lbm_sample_boundary(self._h, ox, oy, wnx, wny, pn, n, pf, pt))
 
     def enable_closure(self, mlp: "Mlp", norm, boundaries: int = 7):
         """norm: 75 floats (feature mean[36], feature 1/std[36], output scale[3]);
         boundaries: bit mask 1 top, 2 bottom, 4 outlet."""
         a = np.ascontiguousarray(norm, dtype=np.float32)
-        assert a.size == 75
+        if a.size != 75:
+            raise LbmError(f"norm needs 75 values; got {a.size}")
         self._mlp_ref = mlp
         check(_lib.lib.lbm_closure_enable(self._h, mlp._h, a.ctypes.data, boundaries))
 
@@ -205,7 +228,9 @@ class Lattice:
 
     def fields_device(self, rho, ux, uy):
         """Fill caller-owned device tensors (float32, [ny][nx], contiguous)."""
-        ptr = [t.data_ptr() if t is not None else None for t in (rho, ux, uy)]
+        n = self.nx * self.ny
+        ptr = [_device_ptr(t, n, name=nm) if t is not None else None
+               for t, nm in ((rho, "rho"), (ux, "ux"), (uy, "uy"))]
         check(_lib.lib.lbm_fields(self._h, *ptr, 1))
 
     def get_populations(self, dtype=np.float32):
@@ -218,16 +243,21 @@ class Lattice:
         f = np.asarray(f)
         dt = 0 if f.dtype == np.float32 else 1
         a = np.ascontiguousarray(f, dtype=np.float32 if dt == 0 else np.float64)
-        assert a.shape == (9, self.ny, self.nx)
+        if a.shape != (9, self.ny, self.nx):
+            raise LbmError(f"populations must have shape (9, {self.ny}, {self.nx}); got {a.shape}")
         check(_lib.lib.lbm_set_populations(self._h, a.ctypes.data, dt, 0))
 
     def get_populations_device(self, t):
+        """Copy the state into a device tensor [9][ny][nx] (float32 or float64)."""
+        ptr = _device_ptr(t, 9 * self.nx * self.ny, ("torch.float32", "torch.float64"), "populations")
         dt = 0 if str(t.dtype) == "torch.float32" else 1
-        check(_lib.lib.lbm_get_populations(self._h, t.data_ptr(), dt, 1))
+        check(_lib.lib.lbm_get_populations(self._h, ptr, dt, 1))
 
     def set_populations_device(self, t):
+        """Load the state from a device tensor [9][ny][nx] (float32 or float64)."""
+        ptr = _device_ptr(t, 9 * self.nx * self.ny, ("torch.float32", "torch.float64"), "populations")
         dt = 0 if str(t.dtype) == "torch.float32" else 1
-        check(_lib.lib.lbm_set_populations(self._h, t.data_ptr(), dt, 1))
+        check(_lib.lib.lbm_set_populations(self._h, ptr, dt, 1))
 
 
 class Ensemble:
@@ -307,6 +337,16 @@ class Ensemble:
         check(_lib.lib.lbm_batch_get_populations(self._h, c, out.ctypes.data, dt, 0))
         return out
 
+    def set_populations(self, c: int, f):
+        """Load case c's state from a host array [9][ny][nx] (float32 or float64)."""
+        p = self.params[c]
+        f = np.asarray(f)
+        dt = 0 if f.dtype == np.float32 else 1
+        a = np.ascontiguousarray(f, dtype=np.float32 if dt == 0 else np.float64)
+        if a.shape != (9, p.ny, p.nx):
+            raise LbmError(f"populations of case {c} must have shape (9, {p.ny}, {p.nx}); got {a.shape}")
+        check(_lib.lib.lbm_batch_set_populations(self._h, c, a.ctypes.data, dt, 0))
+
 
 MLP_PARAMS = 6723
 
@@ -315,8 +355,8 @@ def column_moments(x, stream=None):
     """(mean, std) per column of a device tensor x [M][ncols] (FP64 sums)."""
     M, nc = x.shape
     mean, std = np.empty(nc), np.empty(nc)
-    check(_lib.lib.lbm_column_moments(ctypes.c_void_p(x.data_ptr()), M, nc, mean.ctypes.data, std.ctypes.data,
-                                      _stream_handle(stream)))
+    px = _device_ptr(x, M * nc, name="x")
+    check(_lib.lib.lbm_column_moments(px, M, nc, mean.ctypes.data, std.ctypes.data, _stream_handle(stream)))
     return mean, std
 
 
@@ -329,7 +369,8 @@ class Mlp:
         init = None
         if params is not None:
             self._init = np.ascontiguousarray(params, dtype=np.float32)
-            assert self._init.size == MLP_PARAMS
+            if self._init.size != MLP_PARAMS:
+                raise LbmError(f"the network has {MLP_PARAMS} parameters; got {self._init.size}")
             init = self._init.ctypes.data
         check(_lib.lib.lbm_mlp_create(init, _stream_handle(stream), ctypes.byref(self._h)))
 
@@ -351,6 +392,8 @@ class Mlp:
 
     def set_params(self, p):
         a = np.ascontiguousarray(p, dtype=np.float32)
+        if a.size != MLP_PARAMS:
+            raise LbmError(f"the network has {MLP_PARAMS} parameters; got {a.size}")
         check(_lib.lib.lbm_mlp_set_params(self._h, a.ctypes.data))
 
     def set_norm(self, norm):
@@ -359,26 +402,41 @@ class Mlp:
             check(_lib.lib.lbm_mlp_set_norm(self._h, None))
             return
         self._norm = np.ascontiguousarray(norm, dtype=np.float32)
-        assert self._norm.size == 75
+        if self._norm.size != 75:
+            raise LbmError(f"norm needs 75 values; got {self._norm.size}")
         check(_lib.lib.lbm_mlp_set_norm(self._h, self._norm.ctypes.data))
 
     def set_noise(self, amplitude: float, seed: int = 0):
         check(_lib.lib.lbm_mlp_set_noise(self._h, amplitude, seed))
 
     def forward(self, x, y):
-        check(_lib.lib.lbm_mlp_forward(self._h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
-                                       ctypes.c_void_p(y.data_ptr())))
+        M = x.shape[0]
+        px = _device_ptr(x, 36 * M, name="x")
+        py = _device_ptr(y, 3 * M, name="y")
+        check(_lib.lib.lbm_mlp_forward(self._h, px, M, py))
 
     def train_step(self, x, t, idx, batch: int, lr: float, want_loss=False):
+        """One Adam step on rows idx[0..batch) of x / t (all rows 0..batch-1 if idx is None)."""
+        M = x.shape[0]
+        px = _device_ptr(x, 36 * M, name="x")
+        pt = _device_ptr(t, 3 * M, name="t")
+        if idx is not None:
+            if idx.numel() < batch:
+                raise LbmError(f"idx holds {idx.numel()} rows; batch is {batch}")
+            ip = _device_ptr(idx, idx.numel(), ("torch.int32",), "idx")
+        else:
+            if batch > M:
+                raise LbmError(f"batch {batch} exceeds the {M} rows of x")
+            ip = None
         loss = ctypes.c_double()
-        ip = ctypes.c_void_p(idx.data_ptr()) if idx is not None else None
-        check(_lib.lib.lbm_mlp_train_step(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
-                                          ip, batch, lr, ctypes.byref(loss) if want_loss else None))
+        check(_lib.lib.lbm_mlp_train_step(self._h, px, pt, ip, batch, lr, ctypes.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
 
     def gradient(self, x, t):
+        M = x.shape[0]
+        px = _device_ptr(x, 36 * M, name="x")
+        pt = _device_ptr(t, 3 * M, name="t")
         g = np.empty(MLP_PARAMS, np.float32)
         loss = ctypes.c_double()
-        check(_lib.lib.lbm_mlp_gradient(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
-                                        x.shape[0], g.ctypes.data, ctypes.byref(loss)))
+        check(_lib.lib.lbm_mlp_gradient(self._h, px, pt, M, g.ctypes.data, ctypes.byref(loss)))
         return g, loss.value

@@ -111,6 +111,7 @@ def _load():
         "lbm_batch_forces": (i32, [vp, i32, i64, i64, vp, vp, vp, vp]),
         "lbm_batch_fields": (i32, [vp, i32, vp, vp, vp, ctypes.c_int]),
         "lbm_batch_get_populations": (i32, [vp, i32, vp, ctypes.c_int, ctypes.c_int]),
+        "lbm_batch_set_populations": (i32, [vp, i32, vp, ctypes.c_int, ctypes.c_int]),
         "lbm_batch_variant": (i32, [vp]),
         "lbm_batch_set_variant": (i32, [vp, i32]),
         "lbm_mlp_create": (i32, [vp, vp, ctypes.POINTER(vp)]),

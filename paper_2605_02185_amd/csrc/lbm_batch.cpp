@@ -228,11 +228,11 @@ void free_batch(lbm_batch* b) {
   delete b;
 }
 
-// Four steps per launch with 8-row boundary pieces once the ensemble holds
-// 2^22 nodes: on the 64 cylinder channels of 55 k - 882 k nodes (26.3 M
-// together, MRT) 152 k MLUPS against 83 k for one step per launch and
-// 116-137 k for the other multi-step variants.  Smaller ensembles keep one
-// step per launch, like the single lattices of their size.
+// Starting variant before the autotuner runs (and if it cannot): four steps
+// per launch with 8-row boundary pieces once the ensemble holds 2^22 nodes
+// (on the 64 cylinder channels of 55 k - 882 k nodes, 26.3 M together, MRT:
+// 152 k MLUPS against 83 k for one step per launch and 116-137 k for the
+// other multi-step variants); smaller ensembles one step per launch.
 int batch_default_variant(const lbm_batch* b) {
   int64_t nodes = 0;
   for (const auto& p : b->params) nodes += (int64_t)p.nx * p.ny;
@@ -385,8 +385,11 @@ lbm_status lbm_batch_create(const lbm_params* cases, const int64_t* budgets, int
     const hipError_t e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) st = lbm::set_error(LBM_ERR_HIP, hipGetErrorString(e));
   }
-  if (st == LBM_OK && tune_cache) {
-    // autotune on a scratch ensemble of the same cases (this one is untouched)
+  if (st == LBM_OK) {
+    // autotune on a scratch ensemble of the same cases (this one is
+    // untouched): every variant that can run an ensemble is timed over 48
+    // steps (a multiple of 1, 2, 3 and 4 steps per launch) after 12 warm-up
+    // steps, and the fastest is kept; a cache hit skips the timing
     const std::string key = tune_key(b);
     int best = cache_lookup(tune_cache, key);
     if (!best) {
@@ -395,7 +398,7 @@ lbm_status lbm_batch_create(const lbm_params* cases, const int64_t* budgets, int
       double tbest = 1e30;
       for (int v = 1; s2 == LBM_OK && v <= lbm::num_variants(); ++v) {
         if (!batch_capable(v)) continue;
-        const double t = time_variant(scratch, v, 20);
+        const double t = time_variant(scratch, v, 48);
         if (t < tbest) {
           tbest = t;
           best = v;
@@ -597,6 +600,30 @@ lbm_status lbm_batch_get_populations(lbm_batch* b, int32_t c, void* buf, int dty
   hipError_t e = lbm::launch_pack(own, ca.g, d, dtype, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e == hipSuccess) e = hipMemcpy(buf, d, bytes, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return lbm::set_error(LBM_ERR_HIP, hipGetErrorString(e));
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_populations(lbm_batch* b, int32_t c, const void* buf, int dtype, int on_device) {
+  lbm_status st = check_case(b, c);
+  if (st != LBM_OK) return st;
+  if (!buf || (dtype != 0 && dtype != 1)) return lbm::set_error(LBM_ERR_INVALID_ARG, "bad buffer or dtype");
+  const int k = b->slot_of_case[c];
+  const lbm::CaseArgs& ca = b->hcase[k];
+  // the buffer the case's next step streams from (or its final state)
+  float* own = ca.buf[b->case_cur[k]];
+  const size_t bytes = (size_t)9 * ca.g.nx * ca.g.ny * (dtype ? 8 : 4);
+  if (on_device) {
+    BTRY(lbm::launch_unpack(buf, dtype, ca.g, own, b->stream));
+    BTRY(hipStreamSynchronize(b->stream));
+    return LBM_OK;
+  }
+  void* d = nullptr;
+  BTRY(hipMalloc(&d, bytes));
+  hipError_t e = hipMemcpyAsync(d, buf, bytes, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = lbm::launch_unpack(d, dtype, ca.g, own, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   (void)hipFree(d);
   if (e != hipSuccess) return lbm::set_error(LBM_ERR_HIP, hipGetErrorString(e));
   return LBM_OK;

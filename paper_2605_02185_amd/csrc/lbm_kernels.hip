@@ -1300,12 +1300,16 @@ __global__ __launch_bounds__(256) void multistep_batch_kernel(const CaseArgs* __
 // Folds row blockIdx.x of the per-node force contributions into the FP64
 // history at step *dev_step + blockIdx.x.  The order is fixed: thread t sums
 // nodes t, t+256, ... in turn, each wave reduces its 64 sums by a butterfly
-// of shuffles, and thread 0 adds the four wave sums in wave order.
+// of shuffles, and thread 0 adds the four wave sums in wave order.  The grid
+// holds one block per pending step; when more steps are pending than the
+// history holds, only the newest `cap` of them are written (two blocks would
+// otherwise share a slot in no fixed order).
 __global__ __launch_bounds__(256) void force_reduce_kernel(const double2* __restrict__ partials,
                                                            int nnodes, double* hist, int64_t cap,
                                                            const int64_t* dev_step) {
   __shared__ double2 wsum[4];
   const int j = blockIdx.x;
+  if ((int64_t)j + cap < (int64_t)gridDim.x) return;  // uniform per block
   double sx = 0.0, sy = 0.0;
   for (int i = threadIdx.x; i < nnodes; i += 256) {
     const double2 v = partials[(int64_t)j * nnodes + i];
@@ -1330,12 +1334,14 @@ __global__ __launch_bounds__(256) void force_reduce_kernel(const double2* __rest
 
 // Ensemble version of the two kernels below: block (j, c) folds step j of
 // case c (cases [0, ncases) are the active ones) exactly as
-// force_reduce_kernel folds a single lattice's step.
+// force_reduce_kernel folds a single lattice's step, newest hist_cap steps
+// only.
 __global__ __launch_bounds__(256) void force_reduce_batch_kernel(const CaseArgs* __restrict__ cases,
                                                                  int partial_stride) {
   __shared__ double2 wsum[4];
   const int j = blockIdx.x;
   const CaseArgs& c = cases[blockIdx.y];
+  if ((int64_t)j + c.hist_cap < (int64_t)gridDim.x) return;  // uniform per block
   const double2* __restrict__ part = c.partial + (size_t)j * partial_stride;
   double sx = 0.0, sy = 0.0;
   for (int i = threadIdx.x; i < c.g.n_link_nodes; i += 256) {

@@ -71,19 +71,47 @@ def established(cl, n=3, tol=0.02):
     return max(abs(a / amps[0] - 1) for a in amps[1:]) < tol, amps
 
 
-def window_parity(kw, spin_up, window, periods, require_established=True):
-    note(f"shedding case {kw} spin-up {spin_up} window {window}")
+def _next_upward_crossing(lat, look):
+    """Step of the next upward crossing of the lift through its mean and the
+    lift period, predicted from the last `look` steps of the history."""
+    t = lat.t
+    _, _, _, cl = lat.forces(t - look + 1, look)
+    c = cl - cl.mean()
+    ups = [i + (-c[i]) / (c[i + 1] - c[i]) for i in range(len(c) - 1) if c[i] < 0.0 <= c[i + 1]]
+    assert len(ups) >= 2, "no lift period in the history"
+    T = (ups[-1] - ups[0]) / (len(ups) - 1)
+    return t - look + 1 + ups[-1] + T, T
+
+
+def window_parity(kw, spin_up, window=None, periods=2, require_established=True, period_guess=None):
+    """GPU statistics over a window against the oracle's, from the same state.
+
+    With `period_guess` (steps) the window is placed by phase: after the
+    spin-up the GPU steps on to an eighth of a period before the next upward
+    crossing of the lift, so `periods` whole periods fit in (periods + 1/4)
+    periods of steps, and `window` is derived."""
+    note(f"shedding case {kw} spin-up {spin_up} window {window} periods {periods}")
     d, u = kw["diameter"], kw["u_in"]
     lat = lbm.Lattice(lbm.make_params(**kw))
     lat.step(spin_up)
+    if period_guess:
+        nxt, T = _next_upward_crossing(lat, int(2.5 * period_guess))
+        start = int(nxt - T / 8)
+        while start < lat.t:
+            start += int(round(T))
+        lat.step(start - lat.t)
+        window = int(np.ceil((periods + 0.25) * T))
+        note(f"  lift period {T:.1f} steps; window of {window} steps from step {lat.t}")
+    t0 = lat.t
     state = lat.get_populations(np.float64)
     lat.step(window)
-    _, _, cd, cl = lat.forces(spin_up + 1, window)
+    assert lat.diverged_step() == 0
+    _, _, cd, cl = lat.forces(t0 + 1, window)
     gpu = lbm.shedding_stats(cd, cl, d, u, periods)
-    ok, amps = established(cl, n=min(3, periods - 1))
+    ok, amps = established(cl, n=min(3, periods - 1)) if periods >= 2 else (True, [])
     note(f"  GPU {gpu}, per-period amplitudes {np.round(amps, 5)}")
 
-    o = oracle.Oracle(oracle.OracleParams(**kw))
+    o = oracle.Oracle(oracle.OracleParams(**_oracle_kwargs(kw)))
     o.set_fstar(state)
     fx, fy = [], []
     for first in range(0, window, 2000):

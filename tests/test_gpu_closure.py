@@ -77,10 +77,15 @@ def test_gradient_matches_reference():
     rel = np.linalg.norm(g - ref_g) / np.linalg.norm(ref_g)
     note(f"  gradient relative error {rel:.2e}")
     assert rel < 2e-3
-    # per block of parameters
-    for lo, hi in ((0, 2304), (2304, 2368), (2368, 6464), (6464, 6528), (6528, 6720), (6720, 6723)):
-        r = np.linalg.norm(g[lo:hi] - ref_g[lo:hi]) / (np.linalg.norm(ref_g[lo:hi]) + 1e-30)
-        assert r < 1e-2, (lo, hi, r)
+    # element by element within each parameter block (W1, b1, W2, b2, W3,
+    # b3), against the block's largest reference entry: the forward rule
+    for name, lo, hi in (("W1", 0, 2304), ("b1", 2304, 2368), ("W2", 2368, 6464), ("b2", 6464, 6528),
+                         ("W3", 6528, 6720), ("b3", 6720, 6723)):
+        scale = np.abs(ref_g[lo:hi]).max()
+        err = np.abs(g[lo:hi] - ref_g[lo:hi]) / scale
+        frac = np.mean(err < 1e-5)
+        note(f"  {name}: {hi - lo} entries, within 1e-5 of scale {frac:.4f}, worst {err.max():.2e}")
+        assert frac >= 0.99 and err.max() < 2e-3, name
 
 
 def test_adam_step_matches_reference():
@@ -325,4 +330,5 @@ def test_trained_closure_versus_plain_truncation():
     assert learned["rel_err"]["mean_cd"] < plain["rel_err"]["mean_cd"]
     assert learned["rel_err"]["st"] < plain["rel_err"]["st"]
     assert learned["rel_err"]["mean_cd"] < 0.01 and learned["rel_err"]["st"] < 0.01
+    assert learned["rel_err"]["cl_amp"] < 0.01
     assert learned["speedup"] > 1.0

@@ -160,3 +160,128 @@ def test_ensemble_at_the_reynolds_tau_needs_mrt():
     note(f"  diverged cases in 4000 steps: BGK {out[False]}, MRT {out[True]}")
     assert out[True] == 0
     assert out[False] >= 32
+
+
+def test_smallest_and_largest_of_the_64_cases_match_the_oracle():
+    """The 64-case MRT ensemble in one set of launches (the autotuned
+    variant); its smallest (D = 8) and largest (D = 32) cases start from a
+    seeded disturbed state and after 200 steps their populations, fields and
+    per-step forces are compared with the FP64 oracle's at 1e-5."""
+    import oracle
+    from lbm_inputs import perturbed_populations
+    from parity_util import WT, _oracle_kwargs, compare_state
+
+    cases = ensemble(mrt=True)
+    sizes = [c["nx"] * c["ny"] for c in cases]
+    picks = [int(np.argmin(sizes)), int(np.argmax(sizes))]
+    ens = lbm.Ensemble([lbm.make_params(**kw) for kw in cases])
+    note(f"ensemble variant {lbm.variant_name(ens.variant)}; cases {picks}")
+    f0 = {}
+    for c in picks:
+        kw = cases[c]
+        f0[c] = perturbed_populations(2605 + c, kw["ny"], kw["nx"], WT, 0.03, dtype=np.float32)
+        ens.set_populations(c, f0[c])
+    ens.step(200)
+    ens.sync()
+
+    class _View:
+        """The Lattice-like view compare_state reads."""
+
+        def __init__(self, c):
+            self.c = c
+
+        def fields(self):
+            return ens.fields(self.c)
+
+        def get_populations(self, dtype):
+            return ens.get_populations(self.c, dtype)
+
+    for c in picks:
+        kw = cases[c]
+        note(f"  case {c}: D = {kw['diameter']}, {kw['nx']} x {kw['ny']}, Re = {kw['re']:.2f}")
+        o = oracle.Oracle(oracle.OracleParams(**_oracle_kwargs(kw)))
+        o.set_fstar(f0[c].astype(np.float64))
+        ofx, ofy, bad = o.step(200)
+        assert bad == 0
+        solid = oracle.digitise(oracle.OracleParams(**_oracle_kwargs(kw)))
+        compare_state(_View(c), o, solid)
+        fx, fy, _, _ = ens.forces(c)
+        note(f"  forces: max |dFx| {np.abs(fx - ofx).max():.2e}, max |dFy| {np.abs(fy - ofy).max():.2e}")
+        assert np.abs(fx - ofx).max() < 1e-5 and np.abs(fy - ofy).max() < 1e-5
+
+
+@pytest.mark.timeout(900)
+def test_step_budgets_give_each_case_the_statistics_of_its_own_run():
+    """C4 as the benchmark states it: the 64 MRT cases in one ensemble, each
+    retiring after its own budget of 3000 D steps (150 convective units).
+    Eight cases (D spread over 8..32) are also run alone; their force
+    histories must equal the ensemble's bit for bit, and their shedding
+    statistics over the last five periods (mean Cd, lift amplitude, St) are
+    then the same.  Per-case MLUPS of the ensemble (a case's node updates over
+    the ensemble's wall time) are printed next to those of the separate
+    runs."""
+    import time
+
+    cases = ensemble(mrt=True)
+    budgets = [3000 * c["diameter"] for c in cases]
+    ens = lbm.Ensemble([lbm.make_params(**kw) for kw in cases], budgets=budgets)
+    note(f"ensemble variant {lbm.variant_name(ens.variant)}; budgets {min(budgets)}..{max(budgets)} steps")
+    t0 = time.perf_counter()
+    ens.step(max(budgets))
+    ens.sync()
+    t_ens = time.perf_counter() - t0
+    order = np.argsort([c["diameter"] for c in cases])
+    picks = [int(order[i]) for i in np.linspace(0, len(cases) - 1, 8).round().astype(int)]
+    shedding = 0
+    for c in picks:
+        kw, b = cases[c], budgets[c]
+        steps, bad = ens.info(c)
+        assert (steps, bad) == (b, 0), c
+        lat = lbm.Lattice(lbm.make_params(**kw))
+        t0 = time.perf_counter()
+        lat.step(b)
+        lat.sync()
+        t_alone = time.perf_counter() - t0
+        a = lat.forces()
+        e = ens.forces(c)
+        for x, y in zip(e, a):
+            assert np.array_equal(x, y), c
+        nodes = kw["nx"] * kw["ny"]
+        msg = (f"  case {c}: D {kw['diameter']} Re {kw['re']:.1f}, {b} steps; ensemble {nodes * b / t_ens / 1e6:.0f}"
+               f" MLUPS of its own, alone {nodes * b / t_alone / 1e6:.0f} MLUPS")
+        lat.close()
+        try:
+            se = lbm.shedding_stats(e[2], e[3], kw["diameter"], kw["u_in"], 5)
+            sa = lbm.shedding_stats(a[2], a[3], kw["diameter"], kw["u_in"], 5)
+        except lbm.RangeError:
+            note(msg + "; fewer than five lift periods")
+            continue
+        assert se == sa
+        shedding += 1
+        note(msg + f"; mean Cd {se['mean_cd']:.4f} Cl amp {se['cl_amp']:.4f} St {se['st']:.4f}")
+    assert shedding >= 6
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_short_force_history_keeps_the_newest_steps(graphs):
+    """A history ring smaller than the 96 steps the device folds at once:
+    the newest hist_capacity steps must be the forces a long history holds
+    for the same steps (two steps of a fold never share a slot)."""
+    kw = dict(channel(8, u=0.05), tau=0.6)
+    full = lbm.Lattice(lbm.make_params(**kw))
+    full.step(250)
+    ref = full.forces()
+    for cap in (10, 95):
+        lat = lbm.Lattice(lbm.make_params(**kw, hist_capacity=cap))
+        lat.set_graphs(graphs)
+        lat.step(250)
+        got = lat.forces(251 - cap, cap)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b[-cap:]), cap
+        with pytest.raises(lbm.RangeError):
+            lat.forces(250 - cap, 1)
+    ens = lbm.Ensemble([lbm.make_params(**kw, hist_capacity=10), lbm.make_params(**kw)])
+    ens.step(250)
+    got = ens.forces(0, 241, 10)
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b[-10:])

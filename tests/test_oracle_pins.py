@@ -258,13 +258,14 @@ def test_uniform_flow_is_a_fixed_point_of_every_boundary(wall, outlet):
 
 
 @pytest.mark.parametrize("wall", ALL_WALLS)
-def test_boundary_nodes_get_the_prescribed_moments(wall):
+@pytest.mark.parametrize("outlet", [OUTLET_COPY_ALL, OUTLET_COPY_UNKNOWN])
+def test_boundary_nodes_get_the_prescribed_moments(wall, outlet):
     """After a step from a disturbed state: inlet nodes carry u = (U, 0)
     (Zou-He); NEBB rows carry u = (U, 0); free-slip rows carry v = 0 and
     moving-BB rows a v = 0 only at steady state (not checked)."""
     rng = np.random.default_rng(7)
     U = 0.05
-    p = OracleParams(nx=14, ny=11, u_in=U, tau=0.65, wall=wall)
+    p = OracleParams(nx=14, ny=11, u_in=U, tau=0.65, wall=wall, outlet_mode=outlet)
     o = Oracle(p)
     o.set_f(rand_state(rng, 11, 14, 0.05))
     o.step(1)
@@ -281,19 +282,27 @@ def test_boundary_nodes_get_the_prescribed_moments(wall):
         assert np.allclose(uy[[0, -1], inner], 0.0, atol=1e-15)
     if wall == WALL_FREE_SLIP:
         assert np.allclose(uy[[0, -1], inner], 0.0, atol=1e-15)
-    # outlet copy-all: the last column equals the one before it
     f = o.get_f()
-    assert np.array_equal(f[:, :, -1], f[:, :, -2])
+    if outlet == OUTLET_COPY_ALL:  # the last column equals the one before it
+        assert np.array_equal(f[:, :, -1], f[:, :, -2])
+    else:  # the three populations entering from x = nx, and the corners
+        west = CX < 0
+        assert np.array_equal(f[west][:, rows, -1], f[west][:, rows, -2])
+        if wall != WALL_PERIODIC:
+            assert np.array_equal(f[:, [0, -1], -1], f[:, [0, -1], -2])
 
 
 @pytest.mark.parametrize("wall", ALL_WALLS)
-def test_mirror_symmetry_in_y(wall):
+@pytest.mark.parametrize("outlet", [OUTLET_COPY_ALL, OUTLET_COPY_UNKNOWN])
+def test_mirror_symmetry_in_y(wall, outlet):
     """A state that is mirror-symmetric about the channel mid-height stays
-    so under every wall treatment; this ties the top formulas to the bottom
-    ones (a sign or direction slip on one side breaks it)."""
+    so under every wall and outlet treatment; this ties the top formulas to
+    the bottom ones (a sign or direction slip on one side, or an outlet that
+    copies a different set of directions at the top than at the bottom,
+    breaks it)."""
     rng = np.random.default_rng(8)
     nx, ny = 16, 11
-    p = OracleParams(nx=nx, ny=ny, u_in=0.05, tau=0.7, wall=wall, perturb_amp=0.0)
+    p = OracleParams(nx=nx, ny=ny, u_in=0.05, tau=0.7, wall=wall, perturb_amp=0.0, outlet_mode=outlet)
     o = Oracle(p)
     f = rand_state(rng, ny, nx)
     mirror = [0, 1, 4, 3, 2, 8, 7, 6, 5]  # N<->S, NE<->SE, NW<->SW
@@ -302,6 +311,75 @@ def test_mirror_symmetry_in_y(wall):
     o.step(30)
     g = o.get_f()
     assert np.max(np.abs(g - g[mirror][:, ::-1, :])) < 1e-14
+
+
+def test_copy_unknown_outlet_replaces_exactly_the_populations_with_no_source():
+    """The copy-unknown outlet (Eq. 13 applied to the missing populations,
+    Fig. 2): at the outlet column a population k is unknown after streaming
+    iff its source x - c_k lies outside the lattice, i.e. c_kx = +1 brings
+    nothing in from x = nx.  Derived here from Table 1 and the lattice size
+    alone: the known populations of interior outlet nodes must be the
+    post-collision values pulled along c_k (streaming, Eq. 2), untouched by
+    the outlet, and each unknown one must equal its value at x = nx - 2 after
+    the same step."""
+    rng = np.random.default_rng(21)
+    nx, ny = 13, 9
+    p = OracleParams(nx=nx, ny=ny, u_in=0.04, tau=0.7, wall=WALL_FREE_SLIP, outlet_mode=OUTLET_COPY_UNKNOWN,
+                     perturb_amp=0.0)
+    o = Oracle(p)
+    o.set_f(rand_state(rng, ny, nx, 0.05))
+    fs = o.get_fstar()
+    o.step(1)
+    g = o.get_f()
+    x = nx - 1
+    unknown = [k for k in range(9) if not 0 <= x - CX[k] < nx]
+    assert sorted(unknown) == [3, 6, 7]  # W, NW, SW of Table 1
+    for y in range(2, ny - 2):  # rows whose pull sources are all fluid interior nodes
+        for k in range(9):
+            if k in unknown:
+                assert g[k, y, x] == g[k, y, x - 1], (y, k)
+            else:
+                assert g[k, y, x] == fs[k, y - CY[k], x - CX[k]], (y, k)
+
+
+def test_inlet_corners_are_equilibrium_nodes_of_the_inlet_state():
+    """The inlet corners (the paper is silent; read as Dirichlet nodes of
+    rho = 1, u = (U, 0)): after a step from a disturbed state all nine
+    independent moments of a corner must be those of Eq. 3 at that state,
+    which fixes its nine populations.  The moment values follow from Eq. 3
+    and Table 1: 1, U, 0, 1/3 + U^2, 0, 1/3, 0, U/3 and 1/9 + U^2/3 for
+    1, cx, cy, cx^2, cx cy, cy^2, cx^2 cy, cx cy^2, cx^2 cy^2."""
+    rng = np.random.default_rng(22)
+    U = 0.06
+    for wall in (WALL_FREE_SLIP, WALL_NEBB, WALL_MOVING_BB):
+        p = OracleParams(nx=10, ny=8, u_in=U, tau=0.7, wall=wall)
+        o = Oracle(p)
+        o.set_f(rand_state(rng, 8, 10, 0.05))
+        o.step(1)
+        f = o.get_f()
+        basis = [np.ones(9), CX, CY, CX * CX, CX * CY, CY * CY, CX * CX * CY, CX * CY * CY, CX * CX * CY * CY]
+        want = [1.0, U, 0.0, 1 / 3 + U * U, 0.0, 1 / 3, 0.0, U / 3, 1 / 9 + U * U / 3]
+        for y in (0, 7):
+            got = [float(b @ f[:, y, 0]) for b in basis]
+            assert np.allclose(got, want, atol=1e-15), (wall, y)
+
+
+def test_reference_density_one_is_the_inlet_density_within_a_percent():
+    """Eq. 15 divides by the inlet density; the reading takes rho_ref = 1 (a
+    velocity inlet with an extrapolated outlet fixes no pressure level).  On
+    the D = 10 channel (the benchmark's first configuration) the density the
+    Zou-He inlet carries, averaged over its column and over steps 1000-2000,
+    stays within 1 % of 1, so the reading moves Cd and Cl by less than the
+    1 % the statistics are compared at."""
+    p = OracleParams(nx=410, ny=210, diameter=10, u_in=0.1, tau=0.53)
+    o = Oracle(p)
+    o.step(1000)
+    dens = []
+    for _ in range(10):
+        o.step(100)
+        rho, _, _ = o.fields()
+        dens.append(rho[1:-1, 0].mean())
+    assert abs(np.mean(dens) - 1.0) < 0.01, dens
 
 
 # -------------------------------------------------------------- geometry
