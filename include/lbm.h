@@ -348,6 +348,20 @@ lbm_status lbm_mlp_gradient(lbm_mlp* m, const float* x, const float* t, int64_t 
  * (device), into host arrays.  FP64 sums. */
 lbm_status lbm_column_moments(const float* x, int64_t M, int32_t ncols, double* mean, double* std, void* stream);
 
+/* For callers that cannot allocate device memory (code running under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same as lbm_column_moments, with the same kernel and the same results bit
+ * for bit, but its per-column sums go to a static device array of the
+ * library (2 x 4096 doubles = 64 KiB, held on each device it runs on until
+ * the process ends) instead of a device allocation per call; it calls no
+ * hipMalloc or hipFree.  ncols must lie in [1, 4096] (LBM_ERR_INVALID_ARG
+ * otherwise).  Every call on one device shares that device's array, so
+ * calls that overlap on one device (other threads, other streams) race;
+ * calls in sequence are safe, as each fully rewrites what it reads.
+ * Synchronises `stream`. */
+lbm_status lbm_column_moments_noalloc(const float* x, int64_t M, int32_t ncols, double* mean, double* std,
+                                      void* stream);
+
 /* Training data from a full-domain context: for a wnx x wny window whose
  * node (0, 0) sits at node (ox, oy) of `full`, and n boundary-node indices
  * nodes[] of that window (device), writes the features feat[n][36] and the

@@ -32,7 +32,7 @@ from ._lib import (
 )
 
 __all__ = [
-    "Lattice", "Ensemble", "Mlp", "column_moments", "make_params", "MLP_PARAMS", "validate", "tau_of", "geometry", "shedding_stats", "copy_probe",
+    "Lattice", "Ensemble", "Mlp", "column_moments", "column_moments_noalloc", "make_params", "MLP_PARAMS", "validate", "tau_of", "geometry", "shedding_stats", "copy_probe",
     "num_variants", "variant_name", "LbmError", "DivergedError", "RangeError",
     "WALL_FREE_SLIP", "WALL_PERIODIC", "WALL_NEBB", "WALL_MOVING_BB",
     "OUTLET_COPY_ALL", "OUTLET_COPY_UNKNOWN", "COLLISION_BGK", "COLLISION_MRT", "BOUNCE_HALFWAY", "BOUNCE_INTERP", "BOUNCE_FULLWAY",
@@ -357,6 +357,17 @@ def column_moments(x, stream=None):
     mean, std = np.empty(nc), np.empty(nc)
     px = _device_ptr(x, M * nc, name="x")
     check(_lib.lib.lbm_column_moments(px, M, nc, mean.ctypes.data, std.ctypes.data, _stream_handle(stream)))
+    return mean, std
+
+
+def column_moments_noalloc(x, stream=None):
+    """As column_moments, without a device allocation: the library's static
+    device scratch holds the sums (ncols <= 4096; calls that overlap on one
+    device race)."""
+    M, nc = x.shape
+    mean, std = np.empty(nc), np.empty(nc)
+    px = _device_ptr(x, M * nc, name="x")
+    check(_lib.lib.lbm_column_moments_noalloc(px, M, nc, mean.ctypes.data, std.ctypes.data, _stream_handle(stream)))
     return mean, std
 
 

@@ -124,6 +124,7 @@ def _load():
         "lbm_mlp_train_step": (i32, [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.POINTER(ctypes.c_double)]),
         "lbm_mlp_gradient": (i32, [vp, vp, vp, i64, vp, ctypes.POINTER(ctypes.c_double)]),
         "lbm_column_moments": (i32, [vp, i64, i32, vp, vp, vp]),
+        "lbm_column_moments_noalloc": (i32, [vp, i64, i32, vp, vp, vp]),
         "lbm_sample_boundary": (i32, [vp, i32, i32, i32, i32, vp, i64, vp, vp]),
         "lbm_closure_enable": (i32, [vp, vp, vp, i32]),
         "lbm_closure_set_interval": (i32, [vp, i32]),

@@ -12,6 +12,11 @@
 // Each boundary is seen in a canonical frame whose outward normal is +y (the
 // bottom mirrored, the outlet rotated by a quarter turn), where the missing
 // populations are always S, SW and SE; one network serves all three.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <mutex>
+
 #include "lbm_internal.h"
 
 namespace lbm {
@@ -477,7 +482,8 @@ __global__ __launch_bounds__(256) void closure_kernel(const float* __restrict__ 
   }
 }
 
-// Column sums and sums of squares (FP64) of X [M][ncols]; one block per column.
+// Column sums (out[c]) and sums of squares (out[ncols + c]), FP64, of
+// X [M][ncols]; one block per column, each writing only its own two entries.
 __global__ __launch_bounds__(256) void column_moments_kernel(const float* __restrict__ X, int64_t M,
                                                              int ncols, double* out) {
   __shared__ double s1[256], s2[256];
@@ -499,8 +505,8 @@ __global__ __launch_bounds__(256) void column_moments_kernel(const float* __rest
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[2 * c] = s1[0];
-    out[2 * c + 1] = s2[0];
+    out[c] = s1[0];
+    out[ncols + c] = s2[0];
   }
 }
 
@@ -552,3 +558,68 @@ hipError_t launch_column_moments(const float* X, int64_t M, int ncols, double* o
 }
 
 }  // namespace lbm
+
+// ------------------------------------------------ allocation-free moments
+// The partial results of lbm_column_moments_noalloc live in this array
+// instead of a per-call device allocation.  Host code never uses its name as
+// an address: each device's copy is looked up once with hipGetSymbolAddress
+// and that pointer is what kernels and copies receive.
+namespace {
+
+constexpr int kScratchCols = 4096;
+static __device__ __align__(256) double scratch[2 * kScratchCols];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's copy of `scratch` (looked up on first use), or an error.
+lbm_status scratch_on_current_device(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return lbm::set_error(LBM_ERR_HIP, hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return lbm::set_error(LBM_ERR_INVALID_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      char m[160];
+      snprintf(m, sizeof m, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+      return lbm::set_error(LBM_ERR_HIP, m);
+    }
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" lbm_status lbm_column_moments_noalloc(const float* x, int64_t M, int32_t ncols, double* mean,
+                                                 double* std, void* stream) {
+  if (!x || M < 1 || !mean || !std) return lbm::set_error(LBM_ERR_INVALID_ARG, "bad moments arguments");
+  if (ncols < 1 || ncols > kScratchCols) {
+    char m[128];
+    snprintf(m, sizeof m, "ncols %d outside [1, %d], the columns the static scratch holds", (int)ncols,
+             kScratchCols);
+    return lbm::set_error(LBM_ERR_INVALID_ARG, m);
+  }
+  double* d = nullptr;
+  lbm_status st = scratch_on_current_device(&d);
+  if (st != LBM_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // every entry the kernel's blocks write is its own: nothing to clear first
+  hipError_t e = lbm::launch_column_moments(x, M, ncols, d, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(mean, d, sizeof(double) * ncols, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(std, d + ncols, sizeof(double) * ncols, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return lbm::set_error(LBM_ERR_HIP, hipGetErrorString(e));
+  // the sums sit in mean[] and std[]: turn them into the moments in place
+  for (int c = 0; c < ncols; ++c) {
+    const double a = mean[c] / (double)M, b = std[c] / (double)M;
+    mean[c] = a;
+    std[c] = std::sqrt(std::max(0.0, b - a * a));
+  }
+  return LBM_OK;
+}

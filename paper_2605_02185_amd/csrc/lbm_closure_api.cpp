@@ -192,8 +192,9 @@ lbm_status lbm_column_moments(const float* x, int64_t M, int32_t ncols, double* 
   (void)hipFree(d);
   if (e != hipSuccess) return lbm::set_error(LBM_ERR_HIP, hipGetErrorString(e));
   for (int c = 0; c < ncols; ++c) {
-    mean[c] = h[2 * c] / (double)M;
-    std[c] = std::sqrt(std::max(0.0, h[2 * c + 1] / (double)M - mean[c] * mean[c]));
+    const double a = h[c] / (double)M, b = h[ncols + c] / (double)M;
+    mean[c] = a;
+    std[c] = std::sqrt(std::max(0.0, b - a * a));
   }
   return LBM_OK;
 }
