@@ -349,28 +349,33 @@ def ensemble_result(torch, lbm, steps: int = 1920) -> dict:
 
 
 def closure_result() -> dict:
-    """Learned closure at D = 40 with the bulk-damped MRT collision: train on
-    full-domain samples (Re 80, 100, 120), then the full domain against the
-    truncated window (plain and learned) from the same established state,
-    statistics over the last 25k of 50k steps."""
+    """Learned closure at D = 40 with the bulk-damped MRT collision: data
+    from full-domain runs (Re 80, 100, 120; per-node mean residual and random
+    samples), four networks trained, the one closest to the full domain in
+    the closed loop at the held-out Re = 120 kept; then at Re = 100 the full
+    domain against the truncated window (plain, and learned top, bottom and
+    guarded outlet), every run 300k steps from the initial state, statistics
+    over the last 50k; speedup = the full domain's GPU time over the
+    window's, spin-up included."""
     from paper_2605_02185_amd import closure as C
 
     log = lambda m: print(m, file=sys.stderr, flush=True)
     coll = C.damped_mrt()
     t0 = time.perf_counter()
-    X, T = C.generate(collision=coll, log=log)
+    X, T, bias = C.generate(collision=coll, bias_snapshots=C.BIAS_SNAPSHOTS, log=log)
     t1 = time.perf_counter()
-    net, norm, hist = C.fit(X, T, epochs=20, noise=C.NOISE, log=log)
+    net, norm, sel = C.fit_and_select(X, T, bias, collision=coll, log=log)
     t2 = time.perf_counter()
-    res = C.evaluate({"trunc_learned": (net, norm, C.MASK, 80, C.BETA, C.INTERVAL)}, collision=coll,
-                     settle=C.SETTLE, log=log)
+    nets = {"trunc_learned": dict(net=net, norm=norm, mask=7, taper=80, guard=C.OUTLET_GUARD, bias=bias)}
+    res = C.evaluate(nets, collision=coll, start="cold", log=log)
+    res["collision"] = "MRT, shear rates 1/tau, s_e = s_eps = 0.02"
     res["samples"] = int(X.shape[0])
     res["data_s"] = round(t1 - t0, 2)
-    res["train_s"] = round(t2 - t1, 2)
-    res["val_loss"] = hist[-1]
+    res["train_and_select_s"] = round(t2 - t1, 2)
+    res["selection"] = sel
     err = res["trunc_learned"].get("rel_err")
     res["cd_st_within_1pct"] = bool(err and err["mean_cd"] < 0.01 and err["st"] < 0.01)
-    res["speedup_at_1pct"] = res["trunc_learned"]["speedup"] if res["cd_st_within_1pct"] else None
+    res["cd_cl_st_within_1pct"] = bool(err and max(err.values()) < 0.01)
     return res
 
 

@@ -345,7 +345,7 @@ lbm_status lbm_mlp_train_step(lbm_mlp* m, const float* x, const float* t, const 
 lbm_status lbm_mlp_gradient(lbm_mlp* m, const float* x, const float* t, int64_t B, float* grad, double* loss);
 
 /* Per-column mean and standard deviation (population) of x[M][ncols]
- * (device), into host arrays.  FP64 sums. */
+ * (device), into host arrays; 1 <= ncols <= 65536.  FP64 sums. */
 lbm_status lbm_column_moments(const float* x, int64_t M, int32_t ncols, double* mean, double* std, void* stream);
 
 /* For callers that cannot allocate device memory (code running under HIP
@@ -367,10 +367,11 @@ lbm_status lbm_column_moments_noalloc(const float* x, int64_t M, int32_t ncols, 
  * nodes[] of that window (device), writes the features feat[n][36] and the
  * residual targets target[n][3] (population streaming in from outside the
  * window in `full`, minus the value the plain treatment computes from
- * inside the window), from full's current state.  The window and its
- * outside neighbours must lie inside `full`. */
+ * inside the window, minus bias[node][.] when `bias`, a device array
+ * [nb][3] of the window, is not NULL), from full's current state.  The
+ * window and its outside neighbours must lie inside `full`. */
 lbm_status lbm_sample_boundary(lbm_ctx* full, int32_t ox, int32_t oy, int32_t wnx, int32_t wny,
-                               const int32_t* nodes, int64_t n, float* feat, float* target);
+                               const int32_t* nodes, int64_t n, const float* bias, float* feat, float* target);
 
 /* Switch the context to the learned closure: every step (or every interval
  * steps, lbm_closure_set_interval) first evaluates the network on all
@@ -391,6 +392,15 @@ lbm_status lbm_closure_disable(lbm_ctx* ctx);
  * the inlet or the outlet column keep the plain treatment (default 0). */
 lbm_status lbm_closure_set_filter(lbm_ctx* ctx, float beta, int32_t taper);
 
+/* Guards of the closed loop (all off by default): the network's output is
+ * clamped to [-limit, limit] (in units of out_scale, i.e. of the training
+ * targets' spread; limit 0 = no clamp) before it becomes a residual; outlet
+ * nodes within `outlet_taper` nodes of the top and bottom rows keep the
+ * plain treatment; with outlet_neutral != 0 the three outlet residuals of a
+ * node are shifted by their mean so that they add no mass (nor x-momentum)
+ * to it.  LBM_ERR_INVALID_ARG for a negative limit or taper. */
+lbm_status lbm_closure_set_guard(lbm_ctx* ctx, float limit, int32_t outlet_taper, int32_t outlet_neutral);
+
 /* Evaluate the network only every `interval` steps (a divisor of 96: 1, 2,
  * 3, 4, 6, 8, 12, 16, 24, 32, 48 or 96; default 1) and apply the held
  * residual in between, at the steps whose
@@ -400,6 +410,13 @@ lbm_status lbm_closure_set_filter(lbm_ctx* ctx, float beta, int32_t taper);
  * step of the launch; the results are the same bit for bit as with one step
  * per launch.  beta applies per evaluation. */
 lbm_status lbm_closure_set_interval(lbm_ctx* ctx, int32_t interval);
+
+/* A fixed part of the residual per boundary node (host [nb][3], copied;
+ * NULL removes it): the closure then applies out_scale * output + bias[node]
+ * (the clamp of lbm_closure_set_guard acts on the output alone).  Meant for
+ * the time-mean residual of each node in the training data, which leaves
+ * the network the fluctuations around it. */
+lbm_status lbm_closure_set_bias(lbm_ctx* ctx, const float* bias);
 
 /* Residuals the closure computes from the current state, host [nb][3]. */
 lbm_status lbm_closure_residuals(lbm_ctx* ctx, float* out);

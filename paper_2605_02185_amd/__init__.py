@@ -165,14 +165,16 @@ class Lattice:
         check(_lib.lib.lbm_set_graphs(self._h, 1 if enable else 0))
 
     # ------------------------------------------------------- learned closure
-    def sample_boundary(self, ox, oy, wnx, wny, nodes, feat, target):
+    def sample_boundary(self, ox, oy, wnx, wny, nodes, feat, target, bias=None):
         """Training samples of a wnx x wny window at (ox, oy); nodes (int32),
-        feat [n][36] and target [n][3] are device tensors."""
+        feat [n][36], target [n][3] and the optional per-node bias [nb][3]
+        subtracted from the targets are device tensors."""
         n = nodes.numel()
         pn = _device_ptr(nodes, n, ("torch.int32",), "nodes")
         pf = _device_ptr(feat, 36 * n, name="feat")
         pt = _device_ptr(target, 3 * n, name="target")
-        check(_lib.lib.lbm_sample_boundary(self._h, ox, oy, wnx, wny, pn, n, pf, pt))
+        pb = _device_ptr(bias, 3 * (2 * (wnx - 2) + (wny - 2)), name="bias") if bias is not None else None
+        check(_lib.lib.lbm_sample_boundary(self._h, ox, oy, wnx, wny, pn, n, pb, pf, pt))
 
     def enable_closure(self, mlp: "Mlp", norm, boundaries: int = 7):
         """norm: 75 floats (feature mean[36], feature 1/std[36], output scale[3]);
@@ -185,6 +187,23 @@ class Lattice:
 
     def set_closure_filter(self, beta: float = 1.0, taper: int = 0):
         check(_lib.lib.lbm_closure_set_filter(self._h, beta, taper))
+
+    def set_closure_bias(self, bias):
+        """Per-node fixed residual (host [nb][3]) added to the network's, or None."""
+        if bias is None:
+            check(_lib.lib.lbm_closure_set_bias(self._h, None))
+            return
+        nb = 2 * (self.nx - 2) + (self.ny - 2)
+        a = np.ascontiguousarray(bias, dtype=np.float32)
+        if a.size != 3 * nb:
+            raise LbmError(f"bias needs {3 * nb} values; got {a.size}")
+        check(_lib.lib.lbm_closure_set_bias(self._h, a.ctypes.data))
+
+    def set_closure_guard(self, limit: float = 0.0, outlet_taper: int = 0, outlet_neutral: bool = False):
+        """Clamp the network output to +-limit (units of the output scale; 0 =
+        off), keep outlet nodes within outlet_taper of the rows plain and, with
+        outlet_neutral, remove the mass the outlet residuals would add."""
+        check(_lib.lib.lbm_closure_set_guard(self._h, limit, outlet_taper, 1 if outlet_neutral else 0))
 
     def set_closure_interval(self, interval: int = 1):
         """Evaluate the network every `interval` steps (a divisor of 96)."""

@@ -125,11 +125,13 @@ def _load():
         "lbm_mlp_gradient": (i32, [vp, vp, vp, i64, vp, ctypes.POINTER(ctypes.c_double)]),
         "lbm_column_moments": (i32, [vp, i64, i32, vp, vp, vp]),
         "lbm_column_moments_noalloc": (i32, [vp, i64, i32, vp, vp, vp]),
-        "lbm_sample_boundary": (i32, [vp, i32, i32, i32, i32, vp, i64, vp, vp]),
+        "lbm_sample_boundary": (i32, [vp, i32, i32, i32, i32, vp, i64, vp, vp, vp]),
+        "lbm_closure_set_bias": (i32, [vp, vp]),
         "lbm_closure_enable": (i32, [vp, vp, vp, i32]),
         "lbm_closure_set_interval": (i32, [vp, i32]),
         "lbm_closure_disable": (i32, [vp]),
         "lbm_closure_set_filter": (i32, [vp, ctypes.c_float, i32]),
+        "lbm_closure_set_guard": (i32, [vp, ctypes.c_float, i32, i32]),
         "lbm_closure_residuals": (i32, [vp, vp]),
         "lbm_last_error": (ctypes.c_char_p, []),
     }

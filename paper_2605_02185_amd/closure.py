@@ -34,17 +34,32 @@ def damped_mrt(s_bulk=0.02):
     return dict(collision=COLLISION_MRT, s_rates=(1.0, s_bulk, s_bulk, 1.0, 1.1, 1.0, 1.1, 0.0, 0.0))
 
 
-# Closed-loop settings measured at D = 40 (mean Cd and St of the window
-# within 1 % of the full domain, stable over 50k steps): training-input noise
-# of 0.15 standard deviations, the two rows only (the outlet keeps its
-# extrapolation), rows plain within 2 D of the inlet and outlet, the network
-# evaluated every 8 steps and its output low-passed with beta = 0.08 per
-# evaluation (a time constant of about 100 steps).
+# Closed-loop settings measured at D = 40: training-input noise of 0.15
+# standard deviations, rows plain within 2 D of the inlet and outlet, the
+# network evaluated every 8 steps and its output low-passed with beta = 0.08
+# per evaluation (a time constant of about 100 steps).  MASK = 3 closes the
+# two rows; the outlet (bit 4) needs OUTLET_GUARD: an outlet residual changes
+# the mass of the window, whose level no boundary fixes (a velocity inlet and
+# an extrapolated outlet), and the learned outlet residuals drove the window
+# to diverge within 0.5k-5k steps even when clamped to one standard
+# deviation; shifting the three residuals of each outlet node to a zero sum
+# (no mass, no x-momentum) makes it stable.  OUTLET_GUARD = (output clamp in
+# standard deviations, outlet nodes kept plain next to each row, mass-free
+# outlet residuals).
 NOISE = 0.15
 MASK = 3
 BETA = 0.08
 INTERVAL = 8
-SETTLE = 25000
+OUTLET_GUARD = (4.0, 40, True)
+BIAS_SNAPSHOTS = 3000
+# The closed loop is sensitive to the network's initialisation: over seeds
+# 7-12, mean Cd and St of the window stay within 1 % of the full domain for
+# most, the lift amplitude within 1.6-14 %.  fit_and_select trains one
+# network per seed and keeps the one whose closed-loop window comes closest
+# to the full domain at a held-out Reynolds number (VAL_RE, one of the
+# training runs' but not the one reported).
+SEEDS = (7, 8, 9, 10)
+VAL_RE = 120.0
 
 
 def full_domain(d=40, u=0.05, re=100.0, collision=None):
@@ -66,10 +81,16 @@ def n_boundary(kw):
 
 
 def generate(res=(80.0, 100.0, 120.0), d=40, u=0.05, spin_up=175000, snapshots=50000, every=5,
-             per_snapshot=64, seed=2605, collision=None, log=print):
+             per_snapshot=64, seed=2605, collision=None, bias_snapshots=0, bias_every=25, log=print):
     """Samples from full-domain runs at each Re: after spin_up steps, every
     `every` steps, `per_snapshot` random open-boundary nodes of the window.
-    Returns device tensors X [N][36], T [N][3] (raw features and residuals)."""
+
+    With bias_snapshots > 0 every boundary node is first sampled every
+    bias_every steps after the spin-up (bias_snapshots snapshots, split over
+    the Re); the per-node mean residual over them (bias, [nb][3]) is the
+    fixed part of the closure, and the training targets are the residuals
+    relative to it.  Returns device tensors X [N][36], T [N][3] (raw features
+    and residuals) and the bias (host array, or None)."""
     import torch
 
     wkw, ox, oy = window(d, u, collision=collision)
@@ -79,21 +100,40 @@ def generate(res=(80.0, 100.0, 120.0), d=40, u=0.05, spin_up=175000, snapshots=5
     T = torch.empty((n, 3), dtype=torch.float32, device="cuda")
     rng = np.random.default_rng(seed)
     nodes = torch.from_numpy(rng.integers(0, nb, n).astype(np.int32)).cuda()
-    per_re = [snapshots // len(res) + (1 if i < snapshots % len(res) else 0) for i in range(len(res))]
-    off = 0
-    for re, ns in zip(res, per_re):
-        t0 = time.perf_counter()
+    split = lambda total: [total // len(res) + (1 if i < total % len(res) else 0) for i in range(len(res))]
+    lats = []
+    for re in res:
         lat = Lattice(make_params(**full_domain(d, u, re, collision), hist_capacity=4096))
         lat.step(spin_up)
+        lats.append(lat)
+    bias, bias_dev = None, None
+    if bias_snapshots > 0:
+        allnodes = torch.arange(nb, dtype=torch.int32, device="cuda")
+        fscratch = torch.empty((nb, N_FEATURES), dtype=torch.float32, device="cuda")
+        Tb = torch.empty((bias_snapshots, nb, 3), dtype=torch.float32, device="cuda")
+        k = 0
+        for lat, ns in zip(lats, split(bias_snapshots)):
+            for _ in range(ns):
+                lat.step(bias_every)
+                lat.sample_boundary(ox, oy, wkw["nx"], wkw["ny"], allnodes, fscratch, Tb[k])
+                k += 1
+        mean, _ = column_moments(Tb.view(bias_snapshots, nb * 3))
+        bias = mean.reshape(nb, 3).astype(np.float32)
+        bias_dev = torch.from_numpy(bias).cuda()
+        del Tb, fscratch
+        log(f"closure data: per-node mean residual from {bias_snapshots} snapshots of all {nb} boundary nodes")
+    off = 0
+    for re, lat, ns in zip(res, lats, split(snapshots)):
+        t0 = time.perf_counter()
         for _ in range(ns):
             lat.step(every)
             lat.sample_boundary(ox, oy, wkw["nx"], wkw["ny"], nodes[off:off + per_snapshot],
-                                X[off:off + per_snapshot], T[off:off + per_snapshot])
+                                X[off:off + per_snapshot], T[off:off + per_snapshot], bias_dev)
             off += per_snapshot
         lat.sync()
         lat.close()
-        log(f"closure data: Re {re:g}: {ns} snapshots after {spin_up} steps ({time.perf_counter() - t0:.1f} s)")
-    return X, T
+        log(f"closure data: Re {re:g}: {ns} snapshots ({time.perf_counter() - t0:.1f} s)")
+    return X, T, bias
 
 
 def fit(X, T, epochs=30, batch=4096, lr=1e-3, seed=7, val_frac=0.05, init=None, noise=0.0,
@@ -135,6 +175,32 @@ def fit(X, T, epochs=30, batch=4096, lr=1e-3, seed=7, val_frac=0.05, init=None, 
     return net, norm, hist
 
 
+def fit_and_select(X, T, bias, seeds=SEEDS, val_re=VAL_RE, d=40, u=0.05, collision=None, epochs=20, noise=NOISE,
+                   total=300000, stats_steps=50000, log=print):
+    """One network per seed (fit), each run in the closed loop (rows and
+    guarded outlet, cold start) at Re = val_re against the full domain at
+    that Re; returns (network, norm, table) for the seed whose worst relative
+    error over mean Cd, lift amplitude and St is smallest."""
+    cands = {}
+    for seed in seeds:
+        net, norm, hist = fit(X, T, epochs=epochs, noise=noise, seed=seed, log=lambda m: None)
+        cands[f"seed{seed}"] = dict(net=net, norm=norm, mask=7, taper=2 * d, guard=OUTLET_GUARD, bias=bias,
+                                    val_loss=hist[-1])
+    res = evaluate(cands, d=d, u=u, re=val_re, collision=collision, start="cold", total=total,
+                   stats_steps=stats_steps, log=log)
+    table, best, best_err = {}, None, float("inf")
+    for name, spec in cands.items():
+        err = res[name].get("rel_err")
+        worst = max(err.values()) if err and res[name]["diverged_step"] == 0 else float("inf")
+        table[name] = {"val_loss": spec["val_loss"], "rel_err": err, "worst": worst}
+        if worst < best_err:
+            best, best_err = name, worst
+    if best is None:
+        raise RuntimeError("no candidate network ran stably in the closed loop")
+    log(f"closure select: {best} (worst relative error {best_err:.4f} at Re {val_re:g})")
+    return cands[best]["net"], cands[best]["norm"], {"chosen": best, "val_re": val_re, "candidates": table}
+
+
 def _init_params(rng):
     """He-uniform hidden layers, zero output layer."""
     p = np.zeros(6723, dtype=np.float32)
@@ -156,7 +222,7 @@ def _timed_steps(lat, n):
     return e0.elapsed_time(e1) * 1e-3
 
 
-def _stats(lat, first, n, kw, periods=4):
+def _stats(lat, first, n, kw, periods=8):
     bad = lat.diverged_step()
     if bad:
         return None, bad
@@ -167,50 +233,67 @@ def _stats(lat, first, n, kw, periods=4):
         return None, 0
 
 
-def evaluate(nets, d=40, u=0.05, re=100.0, spin_up=175000, window_steps=25000, collision=None, variant=0,
-             settle=0, log=print):
-    """The full domain is run to established shedding (spin_up steps) and on
-    for settle + window_steps; each truncated run starts from the window cut
-    out of the full state at spin_up and runs the same steps.  Statistics
-    over the last window_steps of both (settle lets the truncated wake adapt
-    to its boundaries first); seconds are GPU time of the settle +
-    window_steps steps.  `nets` maps a label to (network, norm, boundary
-    mask[, taper, beta[, interval]]); the plain truncated run is always
-    included.  `variant` (0: the library's default) selects the truncated
-    runs' kernel."""
+def _run_window(lat, spec):
+    net = spec.get("net")
+    if net is not None:
+        lat.enable_closure(net, spec["norm"], spec.get("mask", MASK))
+        lat.set_closure_filter(spec.get("beta", BETA), spec.get("taper", 80))
+        lat.set_closure_interval(spec.get("interval", INTERVAL))
+        lat.set_closure_guard(*spec.get("guard", (0.0, 0, False)))
+        if spec.get("bias") is not None:
+            lat.set_closure_bias(spec["bias"])
+
+
+def evaluate(nets, d=40, u=0.05, re=100.0, start="cold", total=300000, stats_steps=50000, spin_up=175000,
+             collision=None, variant=0, periods=8, log=print):
+    """Full domain against truncated windows, statistics over the last
+    `stats_steps` steps of every run (about 10 lift periods by default).
+
+    start = "cold": every run starts from the initial state of the hot path
+    (equilibrium of the inlet velocity with its small transverse
+    perturbation) and runs `total` steps, the window with its closure from
+    the first step; seconds are GPU time of all `total` steps, so the
+    window's own spin-up to established shedding is included.
+    start = "cut": the full domain runs `spin_up` steps and each window
+    starts from the full state cut out there; seconds are GPU time of the
+    `total - spin_up` steps after the cut.
+
+    `nets` maps a label to a dict: net, norm, mask (1 top, 2 bottom, 4
+    outlet), taper, beta, interval, guard (limit, outlet taper, mass-free
+    outlet), bias (per-node fixed residual); the plain truncated run is
+    always included.  `variant` (0: the
+    library's default) selects the windows' kernel."""
     import torch
 
     full_kw = full_domain(d, u, re, collision)
     wkw, ox, oy = window(d, u, re, collision)
-    steps = settle + window_steps
-    full = Lattice(make_params(**full_kw, hist_capacity=steps + 4096))
-    full.step(spin_up)
-    S = torch.empty((9, full_kw["ny"], full_kw["nx"]), dtype=torch.float64, device="cuda")
-    full.get_populations_device(S)
-    cut = S[:, oy:oy + wkw["ny"], ox:ox + wkw["nx"]].contiguous()
-    del S
+    full = Lattice(make_params(**full_kw, hist_capacity=stats_steps + 4096))
+    cut = None
+    if start == "cut":
+        full.step(spin_up)
+        S = torch.empty((9, full_kw["ny"], full_kw["nx"]), dtype=torch.float64, device="cuda")
+        full.get_populations_device(S)
+        cut = S[:, oy:oy + wkw["ny"], ox:ox + wkw["nx"]].contiguous()
+        del S
+    steps = total - (spin_up if start == "cut" else 0)
     secs = _timed_steps(full, steps)
-    st, bad = _stats(full, spin_up + settle + 1, window_steps, full_kw)
-    out = {"full": {"stats": st, "seconds": secs, "diverged_step": bad, "nodes": full_kw["nx"] * full_kw["ny"]}}
+    st, bad = _stats(full, full.t - stats_steps + 1, stats_steps, full_kw, periods)
+    out = {"start": start, "total_steps": total, "stats_steps": stats_steps,
+           "full": {"stats": st, "seconds": secs, "diverged_step": bad, "nodes": full_kw["nx"] * full_kw["ny"]}}
     full.close()
     log(f"closure eval: full {json.dumps(out['full'])}")
-    runs = [("trunc_plain", (None, None, 0))] + list(nets.items())
+    runs = [("trunc_plain", {})] + list(nets.items())
     for name, spec in runs:
-        net, norm, mask = spec[:3]
-        taper, beta = (spec[3], spec[4]) if len(spec) > 3 else (0, 1.0)
-        interval = spec[5] if len(spec) > 5 else 1
-        lat = Lattice(make_params(**wkw, hist_capacity=steps + 4096))
+        lat = Lattice(make_params(**wkw, hist_capacity=stats_steps + 4096))
         if variant:
             lat.set_variant(variant)
-        lat.set_populations_device(cut)
-        if net is not None:
-            lat.enable_closure(net, norm, mask)
-            lat.set_closure_filter(beta, taper)
-            lat.set_closure_interval(interval)
+        if cut is not None:
+            lat.set_populations_device(cut)
+        _run_window(lat, spec)
         secs = _timed_steps(lat, steps)
-        st, bad = _stats(lat, settle + 1, window_steps, wkw)
+        st, bad = _stats(lat, lat.t - stats_steps + 1, stats_steps, wkw, periods)
         r = {"stats": st, "seconds": secs, "diverged_step": bad, "nodes": wkw["nx"] * wkw["ny"],
-             "speedup": out["full"]["seconds"] / secs}
+             "speedup": out["full"]["seconds"] / secs, "mask": spec.get("mask", 0)}
         ref = out["full"]["stats"]
         if ref and st:
             r["rel_err"] = {k: abs(st[k] / ref[k] - 1) for k in ("mean_cd", "cl_amp", "st")}
@@ -225,16 +308,12 @@ def main(argv=None):
 
     ap = argparse.ArgumentParser(description="train and evaluate the learned boundary closure")
     ap.add_argument("--d", type=int, default=40)
-    ap.add_argument("--spin-up", type=int, default=175000)
     ap.add_argument("--snapshots", type=int, default=50000)
     ap.add_argument("--epochs", type=int, default=20)
-    ap.add_argument("--window", type=int, default=25000)
     ap.add_argument("--noise", type=float, default=NOISE)
-    ap.add_argument("--mask", type=int, default=MASK, help="closure boundaries: 1 top, 2 bottom, 4 outlet")
-    ap.add_argument("--taper", type=int, default=None, help="rows keep the plain treatment this close to the ends")
-    ap.add_argument("--beta", type=float, default=BETA)
-    ap.add_argument("--interval", type=int, default=INTERVAL)
-    ap.add_argument("--settle", type=int, default=SETTLE)
+    ap.add_argument("--start", choices=("cold", "cut"), default="cold")
+    ap.add_argument("--total", type=int, default=300000)
+    ap.add_argument("--stats", type=int, default=50000)
     ap.add_argument("--bgk", action="store_true", help="BGK instead of the bulk-damped MRT collision")
     ap.add_argument("--save", default=None, help="write the trained weights and norm (.npz)")
     args = ap.parse_args(argv)
@@ -242,14 +321,13 @@ def main(argv=None):
 
     torch.cuda.set_device(0)
     coll = None if args.bgk else damped_mrt()
-    X, T = generate(d=args.d, spin_up=args.spin_up, snapshots=args.snapshots, collision=coll)
-    net, norm, hist = fit(X, T, epochs=args.epochs, noise=args.noise)
+    X, T, bias = generate(d=args.d, snapshots=args.snapshots, collision=coll, bias_snapshots=BIAS_SNAPSHOTS)
+    net, norm, sel = fit_and_select(X, T, bias, d=args.d, collision=coll, epochs=args.epochs, noise=args.noise)
     if args.save:
-        np.savez(args.save, params=net.get_params(), norm=norm, val_loss=np.array(hist))
-    taper = 2 * args.d if args.taper is None else args.taper
-    res = evaluate({"trunc_learned": (net, norm, args.mask, taper, args.beta, args.interval)}, d=args.d,
-                   spin_up=args.spin_up, window_steps=args.window, collision=coll, settle=args.settle)
-    res["val_loss"] = hist
+        np.savez(args.save, params=net.get_params(), norm=norm, bias=bias)
+    nets = {"trunc_rows_outlet": dict(net=net, norm=norm, mask=7, taper=2 * args.d, guard=OUTLET_GUARD, bias=bias)}
+    res = evaluate(nets, d=args.d, start=args.start, total=args.total, stats_steps=args.stats, collision=coll)
+    res["selection"] = sel
     print(json.dumps(res), flush=True)
     return res
 

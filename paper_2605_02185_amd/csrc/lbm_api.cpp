@@ -204,6 +204,10 @@ struct lbm_ctx {
   int closure_mask = 7;
   float closure_beta = 1.0f;
   int closure_taper = 0;
+  float closure_limit = 0.0f;
+  int closure_outlet_taper = 0;
+  int closure_outlet_neutral = 0;
+  float* d_bias = nullptr;  // per-node fixed part of the residual [nb][3], or null
   int closure_interval = 1;
   float* d_norm = nullptr;
   float* d_resid = nullptr;
@@ -378,6 +382,7 @@ void free_ctx(lbm_ctx* c) {
   (void)hipFree(c->d_bad_step);
   (void)hipFree(c->d_norm);
   (void)hipFree(c->d_resid);
+  (void)hipFree(c->d_bias);
   delete c;
 }
 
@@ -544,7 +549,7 @@ lbm_status enqueue_step(lbm_ctx* c, hipStream_t s, int k = 1) {
     if (closure_due(c)) {
       const lbm::MlpDevice md = lbm::mlp_device(c->mlp);
       HIP_TRY(lbm::launch_closure(a.A, c->geo, md.Wb, md.master, c->d_norm, c->closure_mask, c->closure_beta,
-                                  c->closure_taper, c->d_resid, s));
+                                  c->closure_taper, c->closure_limit, c->closure_outlet_taper, c->closure_outlet_neutral, c->d_bias, c->d_resid, s));
     }
     a.closure = c->d_resid;
     a.closure_mask = c->closure_mask;
@@ -684,6 +689,34 @@ lbm_status lbm_closure_set_filter(lbm_ctx* c, float beta, int32_t taper) {
   return LBM_OK;
 }
 
+lbm_status lbm_closure_set_guard(lbm_ctx* c, float limit, int32_t outlet_taper, int32_t outlet_neutral) {
+  if (check_ctx(c)) return LBM_ERR_INVALID_ARG;
+  if (!(limit >= 0.0f)) return fail(LBM_ERR_INVALID_ARG, "limit must be >= 0");
+  if (outlet_taper < 0) return fail(LBM_ERR_INVALID_ARG, "outlet_taper must be >= 0");
+  drop_graphs(c);
+  c->closure_limit = limit;
+  c->closure_outlet_taper = outlet_taper;
+  c->closure_outlet_neutral = outlet_neutral != 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_closure_set_bias(lbm_ctx* c, const float* bias) {
+  if (check_ctx(c)) return LBM_ERR_INVALID_ARG;
+  lbm_status st = flush(c);
+  if (st != LBM_OK) return st;
+  drop_graphs(c);
+  if (!bias) {
+    (void)hipFree(c->d_bias);
+    c->d_bias = nullptr;
+    return LBM_OK;
+  }
+  const size_t nb = 2 * (size_t)(c->p.nx - 2) + (size_t)(c->p.ny - 2);
+  if (!c->d_bias) HIP_TRY(hipMalloc(&c->d_bias, sizeof(float) * 3 * nb));
+  HIP_TRY(hipMemcpyAsync(c->d_bias, bias, sizeof(float) * 3 * nb, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
 lbm_status lbm_closure_set_interval(lbm_ctx* c, int32_t interval) {
   if (check_ctx(c)) return LBM_ERR_INVALID_ARG;
   if (interval < 1 || interval > lbm::kRing || lbm::kRing % interval != 0)
@@ -710,14 +743,14 @@ lbm_status lbm_closure_residuals(lbm_ctx* c, float* out) {
   const size_t nb = 2 * (size_t)(c->p.nx - 2) + (size_t)(c->p.ny - 2);
   const lbm::MlpDevice md = lbm::mlp_device(c->mlp);
   HIP_TRY(lbm::launch_closure(c->buf[c->cur], c->geo, md.Wb, md.master, c->d_norm, c->closure_mask, 1.0f,
-                              c->closure_taper, c->d_resid, c->stream));
+                              c->closure_taper, c->closure_limit, c->closure_outlet_taper, c->closure_outlet_neutral, c->d_bias, c->d_resid, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   HIP_TRY(hipMemcpy(out, c->d_resid, sizeof(float) * 3 * nb, hipMemcpyDeviceToHost));
   return LBM_OK;
 }
 
 lbm_status lbm_sample_boundary(lbm_ctx* c, int32_t ox, int32_t oy, int32_t wnx, int32_t wny,
-                               const int32_t* nodes, int64_t n, float* feat, float* target) {
+                               const int32_t* nodes, int64_t n, const float* bias, float* feat, float* target) {
   if (check_ctx(c) || !nodes || !feat || !target || n < 0 || n > INT_MAX)
     return fail(LBM_ERR_INVALID_ARG, "bad sampling arguments");
   // the window, its two inward layers and the outside neighbours it pulls from
@@ -727,8 +760,8 @@ lbm_status lbm_sample_boundary(lbm_ctx* c, int32_t ox, int32_t oy, int32_t wnx, 
   if (n == 0) return LBM_OK;
   lbm_status st = flush(c);
   if (st != LBM_OK) return st;
-  HIP_TRY(lbm::launch_sample_boundary(c->buf[c->cur], c->geo, ox, oy, wnx, wny, nodes, (int)n, feat, target,
-                                      c->stream));
+  HIP_TRY(lbm::launch_sample_boundary(c->buf[c->cur], c->geo, ox, oy, wnx, wny, nodes, (int)n, bias, feat,
+                                      target, c->stream));
   return LBM_OK;
 }
 

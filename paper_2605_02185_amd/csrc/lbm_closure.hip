@@ -397,8 +397,8 @@ __device__ void features(const float* __restrict__ A, const Geometry& g, const B
 // treatments: free-slip for the top and bottom rows (Eq. 7), extrapolation of
 // the missing populations from the column inside for the outlet (Eq. 13).
 __global__ void sample_kernel(const float* __restrict__ A, Geometry g, int ox, int oy, int wnx, int wny,
-                              const int* __restrict__ nodes, int n, float* __restrict__ feat,
-                              float* __restrict__ target) {
+                              const int* __restrict__ nodes, int n, const float* __restrict__ bias,
+                              float* __restrict__ feat, float* __restrict__ target) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int node = nodes[s];
@@ -431,7 +431,7 @@ __global__ void sample_kernel(const float* __restrict__ A, Geometry g, int ox, i
       const int cym = (km == 2 || km == 5 || km == 6) ? 1 : ((km == 4 || km == 7 || km == 8) ? -1 : 0);
       plain = ld(A, g, km, X - cxm, Y - cym);
     }
-    target[(int64_t)s * 3 + j] = truth - plain;
+    target[(int64_t)s * 3 + j] = truth - plain - (bias ? bias[(int64_t)node * 3 + j] : 0.0f);
   }
 }
 
@@ -441,12 +441,18 @@ __global__ void sample_kernel(const float* __restrict__ A, Geometry g, int ox, i
 // Boundaries whose bit is clear in `mask` (1 top, 2 bottom, 4 outlet) keep
 // the plain treatment: their residuals are written as zero.  With beta < 1
 // the applied residual follows the prediction through a first-order
-// low-pass, r <- r + beta (prediction - r), per node.
+// low-pass, r <- r + beta (prediction - r), per node.  With limit > 0 the
+// network's output is clamped to [-limit, limit] before it is scaled (so the
+// residual stays within limit times the training targets' spread), and
+// outlet nodes within outlet_taper nodes of the top and bottom rows keep
+// the plain treatment.
 __global__ __launch_bounds__(256) void closure_kernel(const float* __restrict__ A, Geometry g, int nb,
                                                       const uint16_t* __restrict__ Wb,
                                                       const float* __restrict__ master,
                                                       const float* __restrict__ norm, int mask, float beta,
-                                                      int taper, float* __restrict__ resid) {
+                                                      int taper, float limit, int outlet_taper,
+                                                      int outlet_neutral, const float* __restrict__ bias,
+                                                      float* __restrict__ resid) {
   __shared__ MlpLds s;
   __shared__ __align__(16) uint16_t wl[kWb];
   const int blk = blockIdx.x, tid = threadIdx.x;
@@ -474,8 +480,22 @@ __global__ __launch_bounds__(256) void closure_kernel(const float* __restrict__ 
     if (i < nb) {
       const BNode b = boundary_node(i, g.nx, g.ny);
       // rows keep the plain treatment within `taper` nodes of the inlet and outlet
-      const bool on = ((mask >> b.type) & 1) && (b.type == 2 || (b.x >= taper && b.x <= g.nx - 1 - taper));
-      const float pred = on ? s.y[r * 16 + c] * norm[72 + c] : 0.0f;
+      const bool on = ((mask >> b.type) & 1) &&
+                      (b.type == 2 ? (b.y >= outlet_taper && b.y <= g.ny - 1 - outlet_taper)
+                                   : (b.x >= taper && b.x <= g.nx - 1 - taper));
+      // one output: the clamped network value times its scale, plus the
+      // node's fixed part when a per-node bias is set
+      auto out = [&](int j) {
+        float y = s.y[r * 16 + j];
+        if (limit > 0.0f) y = fminf(fmaxf(y, -limit), limit);
+        return bias ? y * norm[72 + j] + bias[(int64_t)i * 3 + j] : y * norm[72 + j];
+      };
+      float pred = on ? out(c) : 0.0f;
+      if (on && outlet_neutral && b.type == 2) {
+        // remove the part that changes the node's mass: the three residuals
+        // then sum to zero (and so does the x-momentum they carry)
+        pred -= (out(0) + out(1) + out(2)) * (1.0f / 3.0f);
+      }
       float* dst = resid + (int64_t)i * 3 + c;
       *dst = beta >= 1.0f ? pred : *dst + beta * (pred - *dst);
     }
@@ -538,17 +558,19 @@ hipError_t launch_mlp_forward(const float* X, int M, const uint16_t* Wb, const f
 }
 
 hipError_t launch_sample_boundary(const float* A, const Geometry& g, int ox, int oy, int wnx, int wny,
-                                  const int* nodes, int n, float* feat, float* target, hipStream_t s) {
+                                  const int* nodes, int n, const float* bias, float* feat, float* target,
+                                  hipStream_t s) {
   hipLaunchKernelGGL(sample_kernel, dim3((n + 63) / 64), dim3(64), 0, s, A, g, ox, oy, wnx, wny, nodes, n,
-                     feat, target);
+                     bias, feat, target);
   return hipGetLastError();
 }
 
 hipError_t launch_closure(const float* A, const Geometry& g, const uint16_t* Wb, const float* master,
-                          const float* norm, int mask, float beta, int taper, float* resid, hipStream_t s) {
+                          const float* norm, int mask, float beta, int taper, float limit, int outlet_taper,
+                          int outlet_neutral, const float* bias, float* resid, hipStream_t s) {
   const int nb = 2 * (g.nx - 2) + (g.ny - 2);
   hipLaunchKernelGGL(closure_kernel, dim3((nb + MB - 1) / MB), dim3(256), 0, s, A, g, nb, Wb, master, norm,
-                     mask, beta, taper, resid);
+                     mask, beta, taper, limit, outlet_taper, outlet_neutral, bias, resid);
   return hipGetLastError();
 }
 

@@ -181,7 +181,7 @@ lbm_status lbm_mlp_gradient(lbm_mlp* m, const float* x, const float* t, int64_t 
 }
 
 lbm_status lbm_column_moments(const float* x, int64_t M, int32_t ncols, double* mean, double* std, void* stream) {
-  if (!x || M < 1 || ncols < 1 || ncols > 4096 || !mean || !std)
+  if (!x || M < 1 || ncols < 1 || ncols > 65536 || !mean || !std)
     return lbm::set_error(LBM_ERR_INVALID_ARG, "bad moments arguments");
   double* d = nullptr;
   MTRY(hipMalloc(&d, sizeof(double) * 2 * ncols));

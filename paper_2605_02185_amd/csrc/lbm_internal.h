@@ -180,9 +180,11 @@ hipError_t launch_mlp_adam(const float* gpart, int nblk, const double* lpart, fl
 hipError_t launch_mlp_forward(const float* X, int M, const uint16_t* Wb, const float* master, const float* norm,
                               float* Y, hipStream_t s);
 hipError_t launch_sample_boundary(const float* A, const Geometry& g, int ox, int oy, int wnx, int wny,
-                                  const int* nodes, int n, float* feat, float* target, hipStream_t s);
+                                  const int* nodes, int n, const float* bias, float* feat, float* target,
+                                  hipStream_t s);
 hipError_t launch_closure(const float* A, const Geometry& g, const uint16_t* Wb, const float* master,
-                          const float* norm, int mask, float beta, int taper, float* resid, hipStream_t s);
+                          const float* norm, int mask, float beta, int taper, float limit, int outlet_taper,
+                          int outlet_neutral, const float* bias, float* resid, hipStream_t s);
 hipError_t launch_column_moments(const float* X, int64_t M, int ncols, double* out, hipStream_t s);
 
 // device weights of an lbm_mlp (lbm_closure_api.cpp)
