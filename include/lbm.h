@@ -54,7 +54,9 @@ typedef enum {
 /* Outlet of Eq. 13 (zeroth-order extrapolation from column nx-2). */
 typedef enum {
   LBM_OUTLET_COPY_ALL = 0,    /* all nine populations (Eq. 13 as printed) */
-  LBM_OUTLET_COPY_UNKNOWN = 1 /* only W, NW, SW; all nine at the two outlet corners */
+  LBM_OUTLET_COPY_UNKNOWN = 1 /* only the populations no streaming fills: W, NW, SW, and at the two
+                               * outlet corners also those from beyond the wall row (N, NE at the
+                               * bottom, S, SE at the top) */
 } lbm_outlet;
 
 /* Cylinder wall treatment (Sec. 2.4). */

@@ -19,9 +19,7 @@
  * that forgets one is caught by the finiteness check below.
  *
  * Every pass is pinned by a test against the paper or the mathematics
- * (tests/test_oracle_*.py) except one reading: parity unpinned for the
- * outlet corners' copy of all nine populations from x = nx - 2 (O5), a
- * convention the paper leaves open.
+ * (tests/test_oracle_*.py).
  */
 #include "lbm_oracle.h"
 
@@ -508,21 +506,22 @@ static void walls(oracle* o) {
   }
 }
 
-/* O5: zeroth-order extrapolation of the outlet column (Eq. 13). */
+/* O5: zeroth-order extrapolation of the outlet column (Eq. 13).  Copy-all
+ * takes all nine populations of x = nx - 2; copy-unknown only the ones no
+ * streaming filled (Fig. 2): those whose source x - c_k lies outside the
+ * lattice, i.e. c_kx = -1 and, at the two corners, the ones from beyond the
+ * wall row. */
 static void outlet(oracle* o) {
   if (o->p.x_periodic) return;
   int xo = o->nx - 1, xi = o->nx - 2;
-  int corners = o->p.wall != ORACLE_WALL_PERIODIC;
+  int yper = o->p.wall == ORACLE_WALL_PERIODIC;
   for (int y = 0; y < o->ny; ++y) {
     double* go = o->g + node(o, xo, y) * 9;
     const double* gi = o->g + node(o, xi, y) * 9;
-    int all = o->p.outlet_mode == ORACLE_OUTLET_COPY_ALL || (corners && (y == 0 || y == o->ny - 1));
-    if (all) {
-      for (int k = 0; k < 9; ++k) go[k] = gi[k];
-    } else {
-      go[Wd] = gi[Wd];
-      go[NW] = gi[NW];
-      go[SW] = gi[SW];
+    for (int k = 0; k < 9; ++k) {
+      int sy = y - CY[k];
+      int outside = xo - CX[k] >= o->nx || (!yper && (sy < 0 || sy >= o->ny));
+      if (o->p.outlet_mode == ORACLE_OUTLET_COPY_ALL || outside) go[k] = gi[k];
     }
   }
 }

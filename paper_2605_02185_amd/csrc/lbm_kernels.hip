@@ -441,17 +441,18 @@ __device__ __forceinline__ void general_update(const StepArgs& a, int x, int y, 
   float g[9];
   if (outlet) {
     // Eq. 13: the outlet column takes the corrected populations of x = nx-2
+    // (copy-all), or only those that stream in from outside the lattice
+    // (copy-unknown): W, NW, SW, and at a corner those from beyond its row
     gather(a, nx - 2, y, node_flags(a.g, nx - 2, y), g);
-    if (a.p.outlet_mode == kOutletCopyUnknown && !corner_y) {
+    if (a.p.outlet_mode == kOutletCopyUnknown) {
       float own[9];
       pull(a, x, y, fl, own);
-      g[0] = own[0];
-      g[1] = own[1];
-      g[2] = own[2];
-      g[4] = own[4];
-      g[5] = own[5];
-      g[8] = own[8];
-      closure_outlet(a, y, g);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const bool unknown = CX[k] == -1 || (corner_y && (y == 0 ? CY[k] == 1 : CY[k] == -1));
+        g[k] = unknown ? g[k] : own[k];
+      }
+      if (!corner_y) closure_outlet(a, y, g);
     }
   } else {
     gather(a, x, y, fl, g);
@@ -724,11 +725,15 @@ __device__ __forceinline__ void update_regs(const StepArgs& a, double2* __restri
 #pragma unroll
       for (int k = 0; k < 9; ++k) G[k] = from_left(g[k]);
       if (outlet) {
-        if (a.p.outlet_mode == kOutletCopyUnknown && !corner_y) {
-          g[3] = G[3];
-          g[6] = G[6];
-          g[7] = G[7];
-          closure_outlet(a, y, g);
+        if (a.p.outlet_mode == kOutletCopyUnknown) {
+          // only what streams in from outside: W, NW, SW, and at a corner
+          // the populations from beyond its row
+#pragma unroll
+          for (int k = 0; k < 9; ++k) {
+            const bool unknown = CX[k] == -1 || (corner_y && (y == 0 ? CY[k] == 1 : CY[k] == -1));
+            g[k] = unknown ? G[k] : g[k];
+          }
+          if (!corner_y) closure_outlet(a, y, g);
         } else {
 #pragma unroll
           for (int k = 0; k < 9; ++k) g[k] = G[k];

@@ -285,11 +285,9 @@ def test_boundary_nodes_get_the_prescribed_moments(wall, outlet):
     f = o.get_f()
     if outlet == OUTLET_COPY_ALL:  # the last column equals the one before it
         assert np.array_equal(f[:, :, -1], f[:, :, -2])
-    else:  # the three populations entering from x = nx, and the corners
+    else:  # the three populations entering from x = nx
         west = CX < 0
         assert np.array_equal(f[west][:, rows, -1], f[west][:, rows, -2])
-        if wall != WALL_PERIODIC:
-            assert np.array_equal(f[:, [0, -1], -1], f[:, [0, -1], -2])
 
 
 @pytest.mark.parametrize("wall", ALL_WALLS)
@@ -313,18 +311,21 @@ def test_mirror_symmetry_in_y(wall, outlet):
     assert np.max(np.abs(g - g[mirror][:, ::-1, :])) < 1e-14
 
 
-def test_copy_unknown_outlet_replaces_exactly_the_populations_with_no_source():
+@pytest.mark.parametrize("wall", ALL_WALLS)
+def test_copy_unknown_outlet_replaces_exactly_the_populations_with_no_source(wall):
     """The copy-unknown outlet (Eq. 13 applied to the missing populations,
-    Fig. 2): at the outlet column a population k is unknown after streaming
-    iff its source x - c_k lies outside the lattice, i.e. c_kx = +1 brings
-    nothing in from x = nx.  Derived here from Table 1 and the lattice size
-    alone: the known populations of interior outlet nodes must be the
+    Fig. 2): at an outlet node a population k is unknown after streaming iff
+    its source x - c_k lies outside the lattice: c_kx = +1 brings nothing in
+    from x = nx, and at the two corners nothing comes from beyond the wall
+    row either (with periodic walls the rows wrap and no corner exists).
+    Derived here from Table 1 and the lattice size alone, on every outlet
+    node, corners included: the known populations must be the
     post-collision values pulled along c_k (streaming, Eq. 2), untouched by
     the outlet, and each unknown one must equal its value at x = nx - 2 after
     the same step."""
     rng = np.random.default_rng(21)
     nx, ny = 13, 9
-    p = OracleParams(nx=nx, ny=ny, u_in=0.04, tau=0.7, wall=WALL_FREE_SLIP, outlet_mode=OUTLET_COPY_UNKNOWN,
+    p = OracleParams(nx=nx, ny=ny, u_in=0.04, tau=0.7, wall=wall, outlet_mode=OUTLET_COPY_UNKNOWN,
                      perturb_amp=0.0)
     o = Oracle(p)
     o.set_f(rand_state(rng, ny, nx, 0.05))
@@ -332,14 +333,17 @@ def test_copy_unknown_outlet_replaces_exactly_the_populations_with_no_source():
     o.step(1)
     g = o.get_f()
     x = nx - 1
-    unknown = [k for k in range(9) if not 0 <= x - CX[k] < nx]
-    assert sorted(unknown) == [3, 6, 7]  # W, NW, SW of Table 1
-    for y in range(2, ny - 2):  # rows whose pull sources are all fluid interior nodes
+    for y in range(ny):
+        src = [(x - CX[k], (y - CY[k]) % ny if wall == WALL_PERIODIC else y - CY[k]) for k in range(9)]
+        unknown = [k for k in range(9) if not (0 <= src[k][0] < nx and 0 <= src[k][1] < ny)]
+        if 0 < y < ny - 1 or wall == WALL_PERIODIC:
+            assert sorted(unknown) == [3, 6, 7]  # W, NW, SW of Table 1
         for k in range(9):
             if k in unknown:
                 assert g[k, y, x] == g[k, y, x - 1], (y, k)
             else:
-                assert g[k, y, x] == fs[k, y - CY[k], x - CX[k]], (y, k)
+                sx, sy = src[k]
+                assert g[k, y, x] == fs[k, sy, sx], (y, k)
 
 
 def test_inlet_corners_are_equilibrium_nodes_of_the_inlet_state():
