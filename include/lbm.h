@@ -197,12 +197,13 @@ lbm_status lbm_shedding_stats(const double* cd, const double* cl, int64_t n, dou
  * registers, so one launch reads and writes each population once for S node
  * updates; the steps left over (a remainder of n, or steps between learned-
  * closure evaluations that do not fill a launch) run the one-step kernel.
- * The default of a new context is "t4_h8_s8" from 2^21 nodes, "t3_h8_s2"
+ * The default of a new context is "t4_h16u_s8" from 2^21 nodes, "t3_h16u_s2"
  * from 2^20, "t2_h4_u1" from 2^18 and the one-step "v1_ty1_xcd" (cached
- * stores, each XCD on its own band of rows) below ("_sN": segments that
- * need the boundary code run in pieces of N rows; "_uN": pieces of N rows
- * that load all their rows before any update).  lbm_get_variant
- * reports the variant in use. */
+ * stores, each XCD on its own band of rows) below ("_hH": interior segments
+ * of H rows, "_hHu": whose output rows are stored as they are made; "_sN":
+ * segments that need the boundary code run in pieces of N rows; "_uN":
+ * pieces of N rows that load all their rows before any update).
+ * lbm_get_variant reports the variant in use. */
 int32_t lbm_num_variants(void);
 lbm_status lbm_set_variant(lbm_ctx* ctx, int32_t variant);
 int32_t lbm_get_variant(const lbm_ctx* ctx);
@@ -278,7 +279,8 @@ int32_t lbm_batch_variant(const lbm_batch* b);
 /* Select the ensemble's kernel variant (synchronises the ensemble's stream;
  * also done by the autotuner).  Allowed: the one-step variants without a
  * remapped block order, and the multi-step variants "t3_h8_s2", "t3_h8_s4",
- * "t4_h8_s2", "t4_h8_s4" and "t4_h8_s8", which advance every active case by
+ * "t4_h8_s2", "t4_h8_s4", "t4_h8_s8", "t4_h16u_s8" and "t3_h16u_s2", which
+ * advance every active case by
  * their 3 or 4 steps per launch (the steps a case has left before the active
  * set changes, when fewer, run one per launch on "v1_ty1_nt").  Every
  * variant gives each case the same bits as running it alone.  Returns

@@ -136,6 +136,8 @@ struct Variant {
   int steps;           // time steps per launch (1, or 2-4 with the intermediate states in registers)
   int sub;             // two-step: rows per wave of the segments that need the boundary code
   int unrolled;        // 1: those waves issue every row's loads first, with no row loop
+  int stream;          // multi-step: > 0 for interior waves that store each output row as it is
+                       // made, loading this many rows ahead (bulk_wave_s); 0 holds them to the end
 };
 
 // Kernel launchers (lbm_kernels.hip).  All return the launch status.

@@ -1011,6 +1011,68 @@ __device__ __forceinline__ void bulk_wave_n(const StepArgs& a, int strip, int se
   for (int j = 0; j < H; ++j) store9<NT>(a.B, P, (uint32_t)(y0 + j) * Wp + (uint32_t)x, out[j]);
 }
 
+// Interior segments with each output row stored as soon as it is made
+// (variants "tS_hHu_*").  bulk_wave_n holds the H output rows of a segment
+// in registers and stores them at the end, which keeps loads from waiting
+// behind stores but bounds H (8 rows: 72 registers of outputs), and short
+// segments recompute and re-read their 2(S - 1) halo rows per level for few
+// output rows (14 first-level rows for 8 at S = 4).  Here the registers hold
+// only the three newest rows of each level below the last and the loads in
+// flight, whatever H: at H = 16, 22 + 20 + 18 + 16 rows are updated for
+// 16 x 4 output rows (1.19 times the useful updates against 1.38 at H = 8)
+// and 24 rows of each plane are read for 16 (1.5 against 2).  The row loop
+// is unrolled, like bulk_wave_n's, so every ring index and every test on the
+// row is a constant and the compiler's waits on the loads are exact: rolled
+// over groups of rows (with the rows' tests at run time), the compiler
+// waited for every load in flight once per group and the tall segments ran
+// slower than the short ones despite their smaller traffic.  Stores now sit
+// between loads; the wait for a row's loads also waits for the stores issued
+// before them, which left AHEAD iterations earlier.
+template <bool NT, int H, int S, int COLL, int AHEAD>
+__device__ __forceinline__ void bulk_wave_s(const StepArgs& a, int strip, int seg) {
+  constexpr int h = S - 1, W = 64 - 2 * h;
+  constexpr int R = AHEAD + 1;
+  constexpr int N1 = H + 2 * h;  // first-level rows y0-h .. y0+H+h-1
+  const int lane = (int)(threadIdx.x & 63);
+  if (!interior_segment(a.g, a.t, a.p.x_periodic, strip, seg)) return;
+  const int xs = strip_start(a.g, a.t, a.p.x_periodic, strip);
+  const int y0 = seg * H;
+  const int x = xs - h + lane;
+  const bool out_col = lane >= h && lane < h + W;
+  const uint32_t Pl = (uint32_t)a.g.plane, Wp = (uint32_t)a.g.pitch;
+  float w[S - 1][3][9], pre[R][9];
+#pragma unroll
+  for (int i = 0; i < AHEAD; ++i) load_pull(a, x, y0 - h + i, pre[i]);
+  bool bad[S];
+#pragma unroll
+  for (int l = 0; l < S; ++l) bad[l] = false;
+#pragma unroll
+  for (int i = 0; i < N1; ++i) {
+    if (i + AHEAD < N1) load_pull(a, x, y0 - h + i + AHEAD, pre[(i + AHEAD) % R]);
+    bool b1 = false;
+    collide_t<COLL>(pre[i % R], a.p, w[0][i % 3], b1);
+    if (i >= h && i < h + H) bad[0] |= b1;
+#pragma unroll
+    for (int l = 2; l <= S; ++l) {
+      if (i < 2 * (l - 1)) continue;
+      float c[9];
+      pull_rows(w[l - 2][(i + 1) % 3], w[l - 2][(i + 2) % 3], w[l - 2][i % 3], c);
+      const int q = i - h - (l - 1);  // row - y0 of this level's row
+      if (l < S) {
+        bool b = false;
+        collide_t<COLL>(c, a.p, w[l - 1][i % 3], b);
+        if (q >= 0 && q < H) bad[l - 1] |= b;
+      } else {
+        float out[9];
+        collide_t<COLL>(c, a.p, out, bad[S - 1]);
+        if (out_col) store9<NT>(a.B, Pl, (uint32_t)(y0 + q) * Wp + (uint32_t)x, out);
+      }
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < S; ++l) report_bad(a.bad, bad[l] && out_col, a.slot + l);
+}
+
 // SUB rows (fewer at the segment's or the lattice's end) of a segment that
 // is not interior, with the boundary code on every level: a rolled loop over
 // the first-level rows r, each level l > 1 following on row r - (l - 1).
@@ -1227,7 +1289,7 @@ __global__ __launch_bounds__(256) void step2_kernel(StepArgs a) {
 }
 
 // One launch, S steps; blocks as in step2_kernel.
-template <bool NT, int H, int SUB, int S, int COLL>
+template <bool NT, int H, int SUB, int S, int COLL, int STREAM>
 __global__ __launch_bounds__(256) void multistep_kernel(StepArgs a) {
   constexpr int per = (H + SUB - 1) / SUB;
   const int gen_blocks = (a.n_gen * per + 3) / 4;
@@ -1238,7 +1300,11 @@ __global__ __launch_bounds__(256) void multistep_kernel(StepArgs a) {
     return;
   }
   const int wave = (b - gen_blocks) * 4 + w;
-  if (wave < a.t.ntx * a.t.nty) bulk_wave_n<NT, H, S, COLL>(a, wave % a.t.ntx, wave / a.t.ntx);
+  if (wave >= a.t.ntx * a.t.nty) return;
+  if constexpr (STREAM > 0)
+    bulk_wave_s<NT, H, S, COLL, STREAM>(a, wave % a.t.ntx, wave / a.t.ntx);
+  else
+    bulk_wave_n<NT, H, S, COLL>(a, wave % a.t.ntx, wave / a.t.ntx);
 }
 
 // One step of a whole ensemble: block b processes tile tiles[b] = (case,
@@ -1271,7 +1337,7 @@ __global__ __launch_bounds__(256) void step_batch_kernel(const CaseArgs* __restr
 // with that case's buffers, geometry, physics and force slots, so every case
 // evolves bit for bit as it would alone.  Boundary pieces come first, as in
 // multistep_kernel.
-template <bool NT, int H, int SUB, int S>
+template <bool NT, int H, int SUB, int S, int STREAM>
 __global__ __launch_bounds__(256) void multistep_batch_kernel(const CaseArgs* __restrict__ cases,
                                                               const int2* __restrict__ gen_tasks, int n_gen,
                                                               const int2* __restrict__ bulk_tasks, int n_bulk,
@@ -1298,6 +1364,8 @@ __global__ __launch_bounds__(256) void multistep_batch_kernel(const CaseArgs* __
   a.slot = slot;
   if (general)
     general_wave_n<NT, SUB, S, kEither>(a, code / per, code % per);
+  else if constexpr (STREAM > 0)
+    bulk_wave_s<NT, H, S, kEither, STREAM>(a, code % a.t.ntx, code / a.t.ntx);
   else
     bulk_wave_n<NT, H, S, kEither>(a, code % a.t.ntx, code / a.t.ntx);
 }
@@ -1490,6 +1558,12 @@ constexpr Variant kVariants[] = {
     {"t3_h8_s2", kStrip3, 8, 1, 0, 0, 3, 2},
     {"t4_h8_s2", kStrip4, 8, 1, 0, 0, 4, 2},
     {"t2_h4_u1", kStrip2, 4, 1, 0, 0, 2, 1, 1},
+    {"t4_h16u_s8", kStrip4, 16, 1, 0, 0, 4, 8, 0, 2},
+    {"t4_h8u_s8", kStrip4, 8, 1, 0, 0, 4, 8, 0, 2},
+    {"t4_h12u_s12", kStrip4, 12, 1, 0, 0, 4, 12, 0, 2},
+    {"t4_h24u_s8", kStrip4, 24, 1, 0, 0, 4, 8, 0, 2},
+    {"t3_h16u_s2", kStrip3, 16, 1, 0, 0, 3, 2, 0, 2},
+    {"t4_h16u_s2", kStrip4, 16, 1, 0, 0, 4, 2, 0, 2},
 };
 
 }  // namespace
@@ -1505,14 +1579,18 @@ const Variant& variant(int v) { return kVariants[v - 1]; }
 // their rows first (6.1 against 6.3 us per step at 320 k nodes, 6.3 against
 // 7.1 us at 458 k), where the deeper kernels' boundary chains still set the
 // launch time.  From 2^20 nodes more fused steps win: at 1.4 M nodes three steps with 2-row boundary
-// pieces (145 k MLUPS against 134 k for four and 112 k for two steps), from
-// 2.8 M four steps with 8-row pieces (167 k on the 2.8 M slab, 191 k at
-// 5.5 M, 209 k at 22 M, where one step per launch gives 82 k).  Longer
+// pieces and 16-row interior segments storing rows as they are made (154 k
+// MLUPS against 144 k with 8-row segments holding them, 132 k for four and
+// 108 k for two steps), from
+// 2.8 M four steps with 8-row pieces and 16-row interior segments that store
+// each row as it is made (178 k on the 2.8 M slab, 193 k at 5.5 M, 220 k at
+// 22 M, against 165 k, 191 k and 209 k with 8-row segments holding their
+// outputs; one step per launch gives 82 k at 22 M).  Longer
 // boundary pieces recompute fewer rows but lengthen the serial chain of each
 // boundary wave, which only long launches hide.
 int default_variant(int64_t nodes) {
-  const char* want = nodes >= ((int64_t)1 << 21)   ? "t4_h8_s8"
-                     : nodes >= ((int64_t)1 << 20) ? "t3_h8_s2"
+  const char* want = nodes >= ((int64_t)1 << 21)   ? "t4_h16u_s8"
+                     : nodes >= ((int64_t)1 << 20) ? "t3_h16u_s2"
                      : nodes >= ((int64_t)1 << 18) ? "t2_h4_u1"
                                                    : "v1_ty1_xcd";
   for (int v = 1; v <= num_variants(); ++v)
@@ -1540,13 +1618,15 @@ hipError_t launch_step_batch(const CaseArgs* cases, const int2* tiles, int ntile
 }
 
 // Multi-step variants the ensemble runs (instantiated below).
-#define LBM_TB_LIST(X) X(8, 2, 3) X(8, 4, 3) X(8, 2, 4) X(8, 4, 4) X(8, 8, 4)
+#define LBM_TB_LIST(X) X(8, 2, 3, 0) X(8, 4, 3, 0) X(8, 2, 4, 0) X(8, 4, 4, 0) X(8, 8, 4, 0) X(16, 8, 4, 2) \
+  X(16, 2, 3, 2)
 
 bool multistep_batch_supported(int v) {
   if (v < 1 || v > num_variants()) return false;
   const Variant& var = variant(v);
   if (var.nontemporal || var.steps < 3) return false;
-#define LBM_TB_HAS(H, SUB, S) if (var.tile_y == H && var.sub == SUB && var.steps == S) return true;
+#define LBM_TB_HAS(H, SUB, S, STREAM) \
+  if (var.tile_y == H && var.sub == SUB && var.steps == S && var.stream == STREAM) return true;
   LBM_TB_LIST(LBM_TB_HAS)
 #undef LBM_TB_HAS
   return false;
@@ -1557,11 +1637,11 @@ hipError_t launch_multistep_batch(const CaseArgs* cases, const int2* gen_tasks, 
   if (!multistep_batch_supported(v)) return hipErrorInvalidValue;
   const Variant& var = variant(v);
   const dim3 grid((unsigned)((n_gen + n_bulk + 3) / 4)), block(256);
-#define LBM_TB_LAUNCH(H, SUB, S)                                                                  \
-  if (var.tile_y == H && var.sub == SUB && var.steps == S) {                                       \
-    hipLaunchKernelGGL((multistep_batch_kernel<false, H, SUB, S>), grid, block, 0, s, cases, gen_tasks, \
-                       n_gen, bulk_tasks, n_bulk, cur, slot, partial_stride);                      \
-    return hipGetLastError();                                                                      \
+#define LBM_TB_LAUNCH(H, SUB, S, STREAM)                                                           \
+  if (var.tile_y == H && var.sub == SUB && var.steps == S && var.stream == STREAM) {                 \
+    hipLaunchKernelGGL((multistep_batch_kernel<false, H, SUB, S, STREAM>), grid, block, 0, s, cases,  \
+                       gen_tasks, n_gen, bulk_tasks, n_bulk, cur, slot, partial_stride);             \
+    return hipGetLastError();                                                                        \
   }
   LBM_TB_LIST(LBM_TB_LAUNCH)
 #undef LBM_TB_LAUNCH
@@ -1604,25 +1684,32 @@ hipError_t launch_step(const StepArgs& a, int v, hipStream_t s) {
     const int per = (var.tile_y + var.sub - 1) / var.sub;
     const int blocks = (a.n_gen * per + 3) / 4 + (a.t.ntx * a.t.nty + 3) / 4;
     const dim3 grid((unsigned)blocks), block(256);
-#define LBM_TN(NT, H, SUB, S)                                                            \
-  if (var.nontemporal == NT && var.tile_y == H && var.sub == SUB && var.steps == S) {     \
-    if (a.p.mrt)                                                                          \
-      hipLaunchKernelGGL((multistep_kernel<NT, H, SUB, S, kMrt>), grid, block, 0, s, a);  \
-    else                                                                                  \
-      hipLaunchKernelGGL((multistep_kernel<NT, H, SUB, S, kBgk>), grid, block, 0, s, a);  \
-    return hipGetLastError();                                                            \
+#define LBM_TN(NT, H, SUB, S, STREAM)                                                         \
+  if (var.nontemporal == NT && var.tile_y == H && var.sub == SUB && var.steps == S &&           \
+      var.stream == STREAM) {                                                                    \
+    if (a.p.mrt)                                                                                 \
+      hipLaunchKernelGGL((multistep_kernel<NT, H, SUB, S, kMrt, STREAM>), grid, block, 0, s, a); \
+    else                                                                                         \
+      hipLaunchKernelGGL((multistep_kernel<NT, H, SUB, S, kBgk, STREAM>), grid, block, 0, s, a); \
+    return hipGetLastError();                                                                    \
   }
-    LBM_TN(false, 4, 4, 3)
-    LBM_TN(false, 6, 4, 3)
-    LBM_TN(false, 8, 4, 3)
-    LBM_TN(false, 12, 4, 3)
-    LBM_TN(false, 8, 8, 3)
-    LBM_TN(false, 8, 4, 4)
-    LBM_TN(false, 8, 8, 4)
-    LBM_TN(false, 12, 4, 4)
-    LBM_TN(false, 12, 12, 4)
-    LBM_TN(false, 8, 2, 3)
-    LBM_TN(false, 8, 2, 4)
+    LBM_TN(false, 4, 4, 3, 0)
+    LBM_TN(false, 6, 4, 3, 0)
+    LBM_TN(false, 8, 4, 3, 0)
+    LBM_TN(false, 12, 4, 3, 0)
+    LBM_TN(false, 8, 8, 3, 0)
+    LBM_TN(false, 8, 4, 4, 0)
+    LBM_TN(false, 8, 8, 4, 0)
+    LBM_TN(false, 12, 4, 4, 0)
+    LBM_TN(false, 12, 12, 4, 0)
+    LBM_TN(false, 8, 2, 3, 0)
+    LBM_TN(false, 8, 2, 4, 0)
+    LBM_TN(false, 16, 8, 4, 2)
+    LBM_TN(false, 8, 8, 4, 2)
+    LBM_TN(false, 12, 12, 4, 2)
+    LBM_TN(false, 24, 8, 4, 2)
+    LBM_TN(false, 16, 2, 3, 2)
+    LBM_TN(false, 16, 2, 4, 2)
 #undef LBM_TN
     return hipErrorInvalidValue;
   }

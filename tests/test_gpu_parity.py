@@ -6,6 +6,8 @@ Tolerance: |d rho|, |d u| and |d f*| <= 1e-5 after the stated number of steps
 Integer outputs (geometry, step counters, divergence step) must match exactly;
 repeated runs and kernel variants must match bit for bit.
 """
+import re
+
 import numpy as np
 import pytest
 
@@ -290,21 +292,44 @@ def test_two_step_variants_match_one_step_bitwise(case):
                 assert np.array_equal(a, b), v
 
 
+@pytest.mark.parametrize("name", ["cyl_d40", "cyl_d80"])
+def test_tall_segment_variants_match_one_step_bitwise(name):
+    """Four steps per launch with tall segments (16 to 48 rows, each output
+    row stored as it is made) on lattices large enough that most segments
+    take that interior path: populations and forces after 101 steps (a
+    96-step graph, then plain launches) equal the one-step kernel's bit for
+    bit."""
+    kw = dict(WORKLOADS[name])
+    by_name = {lbm.variant_name(v): v for v in range(1, lbm.num_variants() + 1)}
+    ref = _run_gpu(kw, 101, by_name["v1_ty1_nt"], 77)
+    tall = [n for n in by_name if n.startswith("t4_h") and (int(re.match(r"t4_h(\d+)", n).group(1)) > 12
+                                                         or re.match(r"t4_h\d+u", n))]
+    assert tall
+    for vn in ["t4_h8_s8"] + tall:
+        note(f"  {name} variant {vn}")
+        f, forces = _run_gpu(kw, 101, by_name[vn], 77)
+        assert np.array_equal(f, ref[0]), vn
+        for a, b in zip(forces, ref[1]):
+            if a is not None:
+                assert np.array_equal(a, b), vn
+
+
 def test_default_variant_follows_the_lattice_size():
     """One step per launch below 2^18 nodes (cached stores, XCD bands), two
     from 2^18 (one-row boundary pieces loading all their rows first), three
-    from 2^20 (2-row pieces), four from 2^21 (8-row pieces); variant 0
+    from 2^20 (2-row pieces), four from 2^21 (16-row interior segments
+    storing rows as they are made, 8-row boundary pieces); variant 0
     restores the default."""
     small = lbm.Lattice(lbm.make_params(**WORKLOADS["cyl_d10"]))
     big = lbm.Lattice(lbm.make_params(**WORKLOADS["cyl_d40"]))
     assert lbm.variant_name(small.variant) == "v1_ty1_xcd"
-    assert lbm.variant_name(big.variant) == "t3_h8_s2"
-    for name, want in (("cyl_d20_mrt", "t2_h4_u1"), ("slab_d160_of8", "t4_h8_s8"), ("cyl_d80", "t4_h8_s8"),
-                       ("cyl_d160", "t4_h8_s8")):
+    assert lbm.variant_name(big.variant) == "t3_h16u_s2"
+    for name, want in (("cyl_d20_mrt", "t2_h4_u1"), ("slab_d160_of8", "t4_h16u_s8"), ("cyl_d80", "t4_h16u_s8"),
+                       ("cyl_d160", "t4_h16u_s8")):
         lat = lbm.Lattice(lbm.make_params(**WORKLOADS[name]))
         assert lbm.variant_name(lat.variant) == want, name
         lat.close()
     big.set_variant(1)
     assert big.variant == 1
     big.set_variant(0)
-    assert lbm.variant_name(big.variant) == "t3_h8_s2"
+    assert lbm.variant_name(big.variant) == "t3_h16u_s2"
