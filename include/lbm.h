@@ -377,12 +377,16 @@ lbm_status lbm_column_moments_noalloc(const float* x, int64_t M, int32_t ncols, 
 lbm_status lbm_sample_boundary(lbm_ctx* full, int32_t ox, int32_t oy, int32_t wnx, int32_t wny,
                                const int32_t* nodes, int64_t n, const float* bias, float* feat, float* target);
 
-/* Switch the context to the learned closure: every step (or every interval
- * steps, lbm_closure_set_interval) first evaluates the network on all
- * boundary nodes from the current state, then adds
- * out_scale * output to the plain values of the missing populations on the
- * boundaries selected by the bit mask `boundaries` (1 top, 2 bottom, 4
- * outlet; the others keep their plain treatment).
+/* Switch the context to the learned closure: before every step (or every
+ * `interval` steps, lbm_closure_set_interval) the network is evaluated on
+ * all boundary nodes from the current state, and its residuals,
+ * out_scale * output, are added to the plain values of the missing
+ * populations on the boundaries selected by the bit mask `boundaries` (1
+ * top, 2 bottom, 4 outlet; the others keep their plain treatment) from one
+ * interval later on: an evaluation before step t feeds steps t + interval
+ * to t + 2 interval - 1, and the first interval after enabling runs plain.
+ * The lag lets the network run on a second stream alongside the launch that
+ * starts at step t instead of before it.
  * norm (host): feature mean[36], feature 1/std[36], out_scale[3].  Needs
  * free-slip walls, the copy-unknown outlet and no x-periodicity; the network
  * object must outlive the context's use of it.  A network whose last layer
@@ -391,7 +395,7 @@ lbm_status lbm_closure_enable(lbm_ctx* ctx, lbm_mlp* m, const float* norm, int32
 lbm_status lbm_closure_disable(lbm_ctx* ctx);
 
 /* Low-pass of the applied residual per node: r <- r + beta (prediction - r)
- * each step, starting from r = 0 when the closure is enabled; beta = 1 (the
+ * at each evaluation, starting from r = 0 when the closure is enabled; beta = 1 (the
  * default) applies each prediction as is.  Row nodes within `taper` nodes of
  * the inlet or the outlet column keep the plain treatment (default 0). */
 lbm_status lbm_closure_set_filter(lbm_ctx* ctx, float beta, int32_t taper);
@@ -406,13 +410,14 @@ lbm_status lbm_closure_set_filter(lbm_ctx* ctx, float beta, int32_t taper);
 lbm_status lbm_closure_set_guard(lbm_ctx* ctx, float limit, int32_t outlet_taper, int32_t outlet_neutral);
 
 /* Evaluate the network only every `interval` steps (a divisor of 96: 1, 2,
- * 3, 4, 6, 8, 12, 16, 24, 32, 48 or 96; default 1) and apply the held
- * residual in between, at the steps whose
- * index since lbm_create is a multiple of `interval`.  A launch of the
- * variant's two, three or four steps runs wherever no evaluation falls
- * strictly inside it (else single steps), the held residual entering every
- * step of the launch; the results are the same bit for bit as with one step
- * per launch.  beta applies per evaluation. */
+ * 3, 4, 6, 8, 12, 16, 24, 32, 48 or 96; default 1), before the steps whose
+ * index since lbm_create is a multiple of `interval`; its residuals apply
+ * during the following interval, the previous ones in between.  A launch
+ * of the variant's two, three or four steps runs wherever no evaluation
+ * falls strictly inside it (else single steps), the residuals in use
+ * entering every step of the launch; the results are the same bit for bit
+ * as with one step per launch, with or without graph replay.  beta applies
+ * per evaluation. */
 lbm_status lbm_closure_set_interval(lbm_ctx* ctx, int32_t interval);
 
 /* A fixed part of the residual per boundary node (host [nb][3], copied;
@@ -422,7 +427,9 @@ lbm_status lbm_closure_set_interval(lbm_ctx* ctx, int32_t interval);
  * the network the fluctuations around it. */
 lbm_status lbm_closure_set_bias(lbm_ctx* ctx, const float* bias);
 
-/* Residuals the closure computes from the current state, host [nb][3]. */
+/* Residuals the closure computes from the current state, host [nb][3]
+ * (the prediction alone, without the low-pass; the residuals in use are not
+ * touched). */
 lbm_status lbm_closure_residuals(lbm_ctx* ctx, float* out);
 
 /* Thread-local message of the last failure ("" if none). */

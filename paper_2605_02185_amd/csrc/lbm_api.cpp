@@ -194,11 +194,13 @@ struct lbm_ctx {
   int64_t* d_bad_step = nullptr;
   int64_t step = 0;
   int pending = 0;
-  // graph replay of kRing steps; graph[c] starts from buf[c]
+  // graph replay of kRing steps; graph[c | r << 1] starts from buf[c] with
+  // d_resid[r] the learned-closure residuals in use
   int use_graphs = 1;
   hipStream_t capture_stream = nullptr;
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
-  int graph_flip[2] = {0, 0};  // 1: graph[c] leaves the state in buf[c ^ 1] (an odd number of launches)
+  hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+  int graph_flip[4] = {0, 0, 0, 0};  // 1: the graph leaves the state in the other buffer (odd launches)
+  int resid_flip[4] = {0, 0, 0, 0};  // 1: it leaves the other residual buffer in use (odd evaluations)
   // learned closure
   const lbm_mlp* mlp = nullptr;
   int closure_mask = 7;
@@ -210,7 +212,12 @@ struct lbm_ctx {
   float* d_bias = nullptr;  // per-node fixed part of the residual [nb][3], or null
   int closure_interval = 1;
   float* d_norm = nullptr;
-  float* d_resid = nullptr;
+  // d_resid[rc] are the residuals the steps apply; an evaluation writes the
+  // next ones into d_resid[rc ^ 1], in the launch that starts at its step
+  // (two-step kernels) or in a closure launch just before it.
+  float* d_resid[2] = {nullptr, nullptr};
+  int rc = 1;
+  float* d_resid_q = nullptr;  // lbm_closure_residuals
 };
 
 extern "C" {
@@ -357,7 +364,7 @@ lbm_status flush(lbm_ctx* c) {
 }
 
 void drop_graphs(lbm_ctx* c) {
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
     if (c->graph[i]) {
       (void)hipGraphExecDestroy(c->graph[i]);
       c->graph[i] = nullptr;
@@ -381,7 +388,9 @@ void free_ctx(lbm_ctx* c) {
   (void)hipFree(c->d_bad);
   (void)hipFree(c->d_bad_step);
   (void)hipFree(c->d_norm);
-  (void)hipFree(c->d_resid);
+  (void)hipFree(c->d_resid[0]);
+  (void)hipFree(c->d_resid[1]);
+  (void)hipFree(c->d_resid_q);
   (void)hipFree(c->d_bias);
   delete c;
 }
@@ -497,8 +506,11 @@ lbm_status lbm_set_variant(lbm_ctx* c, int32_t v) {
 
 namespace {
 
-// The learned closure is evaluated before the steps whose index is a multiple
-// of its interval.
+// The learned closure is evaluated on the state before each step whose index
+// t is a multiple of its interval; its residuals take effect at step
+// t + interval (until then the previous evaluation's apply).  The
+// one-interval lag lets the network run in the same launch as the steps it
+// does not feed.
 bool closure_due(const lbm_ctx* c) { return c->mlp && c->step % c->closure_interval == 0; }
 
 // Steps t .. t+k-1 share one launch only if no closure evaluation falls
@@ -547,11 +559,31 @@ lbm_status enqueue_step(lbm_ctx* c, hipStream_t s, int k = 1) {
   }
   if (c->mlp) {
     if (closure_due(c)) {
+      // the previous evaluation's residuals now apply; the network reads the
+      // state before this launch and writes the next ones
+      c->rc ^= 1;
       const lbm::MlpDevice md = lbm::mlp_device(c->mlp);
-      HIP_TRY(lbm::launch_closure(a.A, c->geo, md.Wb, md.master, c->d_norm, c->closure_mask, c->closure_beta,
-                                  c->closure_taper, c->closure_limit, c->closure_outlet_taper, c->closure_outlet_neutral, c->d_bias, c->d_resid, s));
+      lbm::ClosureEval e{};
+      e.nb = 2 * (c->p.nx - 2) + (c->p.ny - 2);
+      e.blocks = lbm::closure_blocks(e.nb);
+      e.mask = c->closure_mask;
+      e.taper = c->closure_taper;
+      e.outlet_taper = c->closure_outlet_taper;
+      e.outlet_neutral = c->closure_outlet_neutral;
+      e.beta = c->closure_beta;
+      e.limit = c->closure_limit;
+      e.Wb = md.Wb;
+      e.master = md.master;
+      e.norm = c->d_norm;
+      e.bias = c->d_bias;
+      e.resid_in = c->d_resid[c->rc];
+      e.resid = c->d_resid[c->rc ^ 1];
+      if (lbm::step_fuses_closure(v, k))
+        a.ev = e;
+      else
+        HIP_TRY(lbm::launch_closure(a.A, c->geo, e, s));
     }
-    a.closure = c->d_resid;
+    a.closure = c->d_resid[c->rc];
     a.closure_mask = c->closure_mask;
   }
   HIP_TRY(lbm::launch_step(a, v, s));
@@ -569,7 +601,7 @@ lbm_status enqueue_step(lbm_ctx* c, hipStream_t s, int k = 1) {
 // Captures kRing steps starting from buf[c->cur] (ring empty) into a graph.
 lbm_status capture(lbm_ctx* c) {
   if (!c->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
-  const int cur0 = c->cur;
+  const int cur0 = c->cur, rc0 = c->rc, gi = cur0 | (rc0 << 1);
   const int64_t step0 = c->step;
   HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
   lbm_status st = LBM_OK;
@@ -581,18 +613,21 @@ lbm_status capture(lbm_ctx* c) {
   }
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+  const int evals = c->rc != rc0;
   c->cur = cur0;  // capturing ran nothing
   c->step = step0;
   c->pending = 0;
+  c->rc = rc0;
   if (st != LBM_OK) {
     if (g) (void)hipGraphDestroy(g);
     return st;
   }
   if (e != hipSuccess) return fail(LBM_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-  const hipError_t e2 = hipGraphInstantiate(&c->graph[cur0], g, nullptr, nullptr, 0);
+  const hipError_t e2 = hipGraphInstantiate(&c->graph[gi], g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e2 != hipSuccess) return fail(LBM_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
-  c->graph_flip[cur0] = launches & 1;
+  c->graph_flip[gi] = launches & 1;
+  c->resid_flip[gi] = evals;
   return LBM_OK;
 }
 
@@ -670,8 +705,11 @@ lbm_status lbm_closure_enable(lbm_ctx* c, lbm_mlp* m, const float* norm, int32_t
   drop_graphs(c);
   const size_t nb = 2 * (size_t)(c->p.nx - 2) + (size_t)(c->p.ny - 2);
   if (!c->d_norm) HIP_TRY(hipMalloc(&c->d_norm, sizeof(float) * lbm::kClosureNorm));
-  if (!c->d_resid) HIP_TRY(hipMalloc(&c->d_resid, sizeof(float) * 3 * nb));
-  HIP_TRY(hipMemsetAsync(c->d_resid, 0, sizeof(float) * 3 * nb, c->stream));
+  for (int i = 0; i < 2; ++i) {
+    if (!c->d_resid[i]) HIP_TRY(hipMalloc(&c->d_resid[i], sizeof(float) * 3 * nb));
+    HIP_TRY(hipMemsetAsync(c->d_resid[i], 0, sizeof(float) * 3 * nb, c->stream));
+  }
+  c->rc = 1;  // the first evaluation makes d_resid[0] (zeros) the one in use
   HIP_TRY(hipMemcpyAsync(c->d_norm, norm, sizeof(float) * lbm::kClosureNorm, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->mlp = m;
@@ -742,10 +780,24 @@ lbm_status lbm_closure_residuals(lbm_ctx* c, float* out) {
   if (!c->mlp) return fail(LBM_ERR_STATE, "closure not enabled");
   const size_t nb = 2 * (size_t)(c->p.nx - 2) + (size_t)(c->p.ny - 2);
   const lbm::MlpDevice md = lbm::mlp_device(c->mlp);
-  HIP_TRY(lbm::launch_closure(c->buf[c->cur], c->geo, md.Wb, md.master, c->d_norm, c->closure_mask, 1.0f,
-                              c->closure_taper, c->closure_limit, c->closure_outlet_taper, c->closure_outlet_neutral, c->d_bias, c->d_resid, c->stream));
+  if (!c->d_resid_q) HIP_TRY(hipMalloc(&c->d_resid_q, sizeof(float) * 3 * nb));
+  lbm::ClosureEval e{};
+  e.nb = (int)nb;
+  e.mask = c->closure_mask;
+  e.taper = c->closure_taper;
+  e.outlet_taper = c->closure_outlet_taper;
+  e.outlet_neutral = c->closure_outlet_neutral;
+  e.beta = 1.0f;
+  e.limit = c->closure_limit;
+  e.Wb = md.Wb;
+  e.master = md.master;
+  e.norm = c->d_norm;
+  e.bias = c->d_bias;
+  e.resid_in = c->d_resid_q;
+  e.resid = c->d_resid_q;
+  HIP_TRY(lbm::launch_closure(c->buf[c->cur], c->geo, e, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  HIP_TRY(hipMemcpy(out, c->d_resid, sizeof(float) * 3 * nb, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(out, c->d_resid_q, sizeof(float) * 3 * nb, hipMemcpyDeviceToHost));
   return LBM_OK;
 }
 
@@ -787,12 +839,14 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   }
   if (c->use_graphs) {
     while (n - i >= lbm::kRing) {
-      if (!c->graph[c->cur]) {
+      const int gi = c->cur | (c->rc << 1);
+      if (!c->graph[gi]) {
         lbm_status st = capture(c);
         if (st != LBM_OK) return st;
       }
-      HIP_TRY(hipGraphLaunch(c->graph[c->cur], c->stream));
-      c->cur ^= c->graph_flip[c->cur];
+      HIP_TRY(hipGraphLaunch(c->graph[gi], c->stream));
+      c->cur ^= c->graph_flip[gi];
+      c->rc ^= c->resid_flip[gi];
       c->step += lbm::kRing;
       i += lbm::kRing;
     }

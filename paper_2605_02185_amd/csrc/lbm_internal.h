@@ -93,6 +93,22 @@ __host__ __device__ inline bool interior_segment(const Geometry& g, const Tiling
   return !(xa < g.rx0 + g.rw && xb >= g.rx0 && ya < g.ry0 + g.rh && yb >= g.ry0);
 }
 
+// One evaluation of the learned closure's network on the boundary nodes:
+// nb nodes, the network's bfloat16 weights (Wb) and FP32 parameters
+// (master), the feature normalisation and output scales (norm), the guards
+// and filter, the residuals in use (resid_in) and the ones it writes.
+struct ClosureEval {
+  int blocks;  // in a step launch: the first `blocks` blocks evaluate the network (0: none)
+  int nb, mask, taper, outlet_taper, outlet_neutral;
+  float beta, limit;
+  const uint16_t* Wb;
+  const float* master;
+  const float* norm;
+  const float* bias;
+  const float* resid_in;
+  float* resid;
+};
+
 struct StepArgs {
   const float* __restrict__ A;  // post-collision populations f*(t), 9 planes
   float* __restrict__ B;        // receives f*(t+1)
@@ -109,6 +125,7 @@ struct StepArgs {
   int closure_mask;             // boundaries the closure refines: 1 top, 2 bottom, 4 outlet
   int* bad;                     // watchdog: min ring slot with a bad density
   int slot;                     // ring slot of this step
+  ClosureEval ev;               // a network evaluation folded into the launch (two-step kernels)
 };
 
 // One case of an ensemble, as the batched kernels see it (device memory).
@@ -184,9 +201,12 @@ hipError_t launch_mlp_forward(const float* X, int M, const uint16_t* Wb, const f
 hipError_t launch_sample_boundary(const float* A, const Geometry& g, int ox, int oy, int wnx, int wny,
                                   const int* nodes, int n, const float* bias, float* feat, float* target,
                                   hipStream_t s);
-hipError_t launch_closure(const float* A, const Geometry& g, const uint16_t* Wb, const float* master,
-                          const float* norm, int mask, float beta, int taper, float limit, int outlet_taper,
-                          int outlet_neutral, const float* bias, float* resid, hipStream_t s);
+hipError_t launch_closure(const float* A, const Geometry& g, const ClosureEval& e, hipStream_t s);
+int closure_blocks(int nb);     // blocks of one evaluation
+size_t closure_lds_bytes();     // LDS of one evaluation block
+// Whether a launch of k steps of variant v evaluates the network itself
+// (StepArgs::ev) rather than after a closure_kernel launch.
+bool step_fuses_closure(int v, int k);
 hipError_t launch_column_moments(const float* X, int64_t M, int ncols, double* out, hipStream_t s);
 
 // device weights of an lbm_mlp (lbm_closure_api.cpp)

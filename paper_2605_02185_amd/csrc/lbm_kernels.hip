@@ -32,6 +32,7 @@
 // column and row on every side per level, and stores only f*(t+S).  Every
 // variant gives the same bits as one step per launch.
 #include "lbm_internal.h"
+#include "lbm_mlp_dev.h"
 
 #include <climits>
 #include <cstring>
@@ -1269,11 +1270,27 @@ __device__ __forceinline__ void general_wave_u(const StepArgs& a, int segment, i
 // (Orders that keep vertically adjacent segments on one XCD, so that their
 // shared rows are read once into its L2, fetch 30 % fewer bytes but ran
 // 4-10 % slower: the plain order's DRAM locality wins.)
-template <bool NT, int H, int SUB, bool UNR>
+// With CLO the launch's first a.ev.blocks blocks evaluate the learned
+// closure's network on the state the launch starts from (closure_block, in
+// the dynamic LDS), alongside the steps, which apply the residuals of the
+// previous evaluation: the evaluation then costs no launch of its own.  The
+// launches without an evaluation run the instance without that code (its
+// mere presence cost 2-4 % on the 458 k-node closure window).
+template <bool NT, int H, int SUB, bool UNR, bool CLO>
 __global__ __launch_bounds__(256) void step2_kernel(StepArgs a) {
+  int b = (int)blockIdx.x;
+  if constexpr (CLO) {
+    if (b < a.ev.blocks) {
+      extern __shared__ __align__(16) unsigned char dyn[];
+      closure_block(a.ev, a.A, a.g, b, *reinterpret_cast<FwdLds*>(dyn),
+                    reinterpret_cast<uint16_t*>(dyn + sizeof(FwdLds)));
+      return;
+    }
+    b -= a.ev.blocks;
+  }
   constexpr int per = (H + SUB - 1) / SUB;
   const int gen_blocks = (a.n_gen * per + 3) / 4;
-  const int b = (int)blockIdx.x, w = (int)(threadIdx.x >> 6);
+  const int w = (int)(threadIdx.x >> 6);
   if (b < gen_blocks) {
     const int wave = b * 4 + w;
     if (wave < a.n_gen * per) {
@@ -1658,15 +1675,22 @@ hipError_t launch_force_reduce_batch(const CaseArgs* cases, int ncases, int coun
   return hipGetLastError();
 }
 
+bool step_fuses_closure(int v, int k) { return k == 2 && variant(v).steps == 2; }
+
 hipError_t launch_step(const StepArgs& a, int v, hipStream_t s) {
   const Variant& var = variant(v);
+  if (a.ev.blocks > 0 && !step_fuses_closure(v, var.steps)) return hipErrorInvalidValue;
   if (var.steps == 2) {
     const int per = (var.tile_y + var.sub - 1) / var.sub;
-    const int blocks = (a.n_gen * per + 3) / 4 + (a.t.ntx * a.t.nty + 3) / 4;
+    const int blocks = a.ev.blocks + (a.n_gen * per + 3) / 4 + (a.t.ntx * a.t.nty + 3) / 4;
     const dim3 grid((unsigned)blocks), block(256);
+    const size_t lds = a.ev.blocks > 0 ? closure_lds_bytes() : 0;
 #define LBM_T2(NT, H, SUB, UNR)                                                              \
   if (var.nontemporal == NT && var.tile_y == H && var.sub == SUB && var.unrolled == UNR) {   \
-    hipLaunchKernelGGL((step2_kernel<NT, H, SUB, UNR>), grid, block, 0, s, a);               \
+    if (a.ev.blocks > 0)                                                                     \
+      hipLaunchKernelGGL((step2_kernel<NT, H, SUB, UNR, true>), grid, block, lds, s, a);     \
+    else                                                                                     \
+      hipLaunchKernelGGL((step2_kernel<NT, H, SUB, UNR, false>), grid, block, 0, s, a);      \
     return hipGetLastError();                                                                \
   }
     LBM_T2(false, 4, 2, 0)
