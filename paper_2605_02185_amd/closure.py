@@ -62,6 +62,21 @@ SEEDS = (7, 8, 9, 10)
 VAL_RE = 120.0
 
 
+def scaled(d=40):
+    """The D = 40 settings carried to diameter d (U fixed): step counts scale
+    with the flow time D/U, the rows' plain taper and the outlet guard's with
+    D.  Above D = 40 the window is large enough for three-step launches, so
+    the network is evaluated every 12 steps (a whole number of them), with
+    the low-pass's time constant (interval / beta steps) scaled with D.  At
+    d = 40 this is exactly the settings above."""
+    f = d / 40.0
+    interval = INTERVAL if d <= 40 else 12
+    return dict(spin_up=int(round(175000 * f)), every=max(1, int(round(5 * f))),
+                bias_every=max(1, int(round(25 * f))), total=int(round(300000 * f)),
+                stats=int(round(50000 * f)), interval=interval, beta=min(1.0, BETA * interval / (INTERVAL * f)),
+                guard=(OUTLET_GUARD[0], int(round(OUTLET_GUARD[1] * f)), OUTLET_GUARD[2]), taper=2 * d)
+
+
 def full_domain(d=40, u=0.05, re=100.0, collision=None):
     """The 41 D x 21 D channel; `collision` (keyword arguments of make_params,
     e.g. MRT rates) applies to both the full and the truncated lattice."""
@@ -176,16 +191,19 @@ def fit(X, T, epochs=30, batch=4096, lr=1e-3, seed=7, val_frac=0.05, init=None, 
 
 
 def fit_and_select(X, T, bias, seeds=SEEDS, val_re=VAL_RE, d=40, u=0.05, collision=None, epochs=20, noise=NOISE,
-                   total=300000, stats_steps=50000, log=print):
+                   total=None, stats_steps=None, log=print):
     """One network per seed (fit), each run in the closed loop (rows and
     guarded outlet, cold start) at Re = val_re against the full domain at
     that Re; returns (network, norm, table) for the seed whose worst relative
     error over mean Cd, lift amplitude and St is smallest."""
+    sc = scaled(d)
+    total = sc["total"] if total is None else total
+    stats_steps = sc["stats"] if stats_steps is None else stats_steps
     cands = {}
     for seed in seeds:
         net, norm, hist = fit(X, T, epochs=epochs, noise=noise, seed=seed, log=lambda m: None)
-        cands[f"seed{seed}"] = dict(net=net, norm=norm, mask=7, taper=2 * d, guard=OUTLET_GUARD, bias=bias,
-                                    val_loss=hist[-1])
+        cands[f"seed{seed}"] = dict(net=net, norm=norm, mask=7, taper=sc["taper"], guard=sc["guard"], bias=bias,
+                                    interval=sc["interval"], beta=sc["beta"], val_loss=hist[-1])
     res = evaluate(cands, d=d, u=u, re=val_re, collision=collision, start="cold", total=total,
                    stats_steps=stats_steps, log=log)
     table, best, best_err = {}, None, float("inf")
@@ -312,8 +330,8 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--noise", type=float, default=NOISE)
     ap.add_argument("--start", choices=("cold", "cut"), default="cold")
-    ap.add_argument("--total", type=int, default=300000)
-    ap.add_argument("--stats", type=int, default=50000)
+    ap.add_argument("--total", type=int, default=None, help="steps per run (default: 300k at D = 40, scaled with D)")
+    ap.add_argument("--stats", type=int, default=None, help="steps of statistics (default: 50k at D = 40, scaled)")
     ap.add_argument("--bgk", action="store_true", help="BGK instead of the bulk-damped MRT collision")
     ap.add_argument("--save", default=None, help="write the trained weights and norm (.npz)")
     args = ap.parse_args(argv)
@@ -321,12 +339,20 @@ def main(argv=None):
 
     torch.cuda.set_device(0)
     coll = None if args.bgk else damped_mrt()
-    X, T, bias = generate(d=args.d, snapshots=args.snapshots, collision=coll, bias_snapshots=BIAS_SNAPSHOTS)
-    net, norm, sel = fit_and_select(X, T, bias, d=args.d, collision=coll, epochs=args.epochs, noise=args.noise)
+    sc = scaled(args.d)
+    total = sc["total"] if args.total is None else args.total
+    stats = sc["stats"] if args.stats is None else args.stats
+    X, T, bias = generate(d=args.d, snapshots=args.snapshots, collision=coll, bias_snapshots=BIAS_SNAPSHOTS,
+                          spin_up=sc["spin_up"], every=sc["every"], bias_every=sc["bias_every"])
+    net, norm, sel = fit_and_select(X, T, bias, d=args.d, collision=coll, epochs=args.epochs, noise=args.noise,
+                                    total=total, stats_steps=stats)
     if args.save:
         np.savez(args.save, params=net.get_params(), norm=norm, bias=bias)
-    nets = {"trunc_rows_outlet": dict(net=net, norm=norm, mask=7, taper=2 * args.d, guard=OUTLET_GUARD, bias=bias)}
-    res = evaluate(nets, d=args.d, start=args.start, total=args.total, stats_steps=args.stats, collision=coll)
+    nets = {"trunc_rows_outlet": dict(net=net, norm=norm, mask=7, taper=sc["taper"], guard=sc["guard"], bias=bias,
+                                      interval=sc["interval"], beta=sc["beta"])}
+    res = evaluate(nets, d=args.d, start=args.start, total=total, stats_steps=stats, collision=coll,
+                   spin_up=sc["spin_up"])
+    res["settings"] = sc
     res["selection"] = sel
     print(json.dumps(res), flush=True)
     return res
