@@ -1604,9 +1604,12 @@ const Variant& variant(int v) { return kVariants[v - 1]; }
 // 22 M, against 165 k, 191 k and 209 k with 8-row segments holding their
 // outputs; one step per launch gives 82 k at 22 M).  Longer
 // boundary pieces recompute fewer rows but lengthen the serial chain of each
-// boundary wave, which only long launches hide.
+// boundary wave, which only long launches hide: from 2^24 nodes 12-row
+// segments with 12-row pieces are about 1 % faster (397-400 against 401-403
+// us per launch at 22 M), and up to 8 % slower on the slab.
 int default_variant(int64_t nodes) {
-  const char* want = nodes >= ((int64_t)1 << 21)   ? "t4_h16u_s8"
+  const char* want = nodes >= ((int64_t)1 << 24)   ? "t4_h12u_s12"
+                     : nodes >= ((int64_t)1 << 21) ? "t4_h16u_s8"
                      : nodes >= ((int64_t)1 << 20) ? "t3_h16u_s2"
                      : nodes >= ((int64_t)1 << 18) ? "t2_h4_u1"
                                                    : "v1_ty1_xcd";
