@@ -60,6 +60,10 @@ BIAS_SNAPSHOTS = 3000
 # training runs' but not the one reported).
 SEEDS = (7, 8, 9, 10)
 VAL_RE = 120.0
+# Seeds whose lift amplitude at the held-out Re is off by more than this are
+# passed over: among the rest the one closest in mean Cd and St is kept (the
+# closure's target is those two within 1 %).
+CL_BOUND = 0.05
 
 
 def scaled(d=40):
@@ -194,8 +198,9 @@ def fit_and_select(X, T, bias, seeds=SEEDS, val_re=VAL_RE, d=40, u=0.05, collisi
                    total=None, stats_steps=None, log=print):
     """One network per seed (fit), each run in the closed loop (rows and
     guarded outlet, cold start) at Re = val_re against the full domain at
-    that Re; returns (network, norm, table) for the seed whose worst relative
-    error over mean Cd, lift amplitude and St is smallest."""
+    that Re; returns (network, norm, table) for the seed whose larger
+    relative error of mean Cd and St is smallest among those whose lift
+    amplitude error is below CL_BOUND (all seeds when none is)."""
     sc = scaled(d)
     total = sc["total"] if total is None else total
     stats_steps = sc["stats"] if stats_steps is None else stats_steps
@@ -209,13 +214,17 @@ def fit_and_select(X, T, bias, seeds=SEEDS, val_re=VAL_RE, d=40, u=0.05, collisi
     table, best, best_err = {}, None, float("inf")
     for name, spec in cands.items():
         err = res[name].get("rel_err")
-        worst = max(err.values()) if err and res[name]["diverged_step"] == 0 else float("inf")
-        table[name] = {"val_loss": spec["val_loss"], "rel_err": err, "worst": worst}
-        if worst < best_err:
-            best, best_err = name, worst
+        ok = bool(err) and res[name]["diverged_step"] == 0
+        worst = max(err["mean_cd"], err["st"]) if ok else float("inf")
+        table[name] = {"val_loss": spec["val_loss"], "rel_err": err, "worst_cd_st": worst,
+                       "cl_ok": ok and err["cl_amp"] < CL_BOUND}
+    pool = [n for n in table if table[n]["cl_ok"]] or list(table)
+    for name in pool:
+        if table[name]["worst_cd_st"] < best_err:
+            best, best_err = name, table[name]["worst_cd_st"]
     if best is None:
         raise RuntimeError("no candidate network ran stably in the closed loop")
-    log(f"closure select: {best} (worst relative error {best_err:.4f} at Re {val_re:g})")
+    log(f"closure select: {best} (larger of the mean Cd and St errors {best_err:.4f} at Re {val_re:g})")
     return cands[best]["net"], cands[best]["norm"], {"chosen": best, "val_re": val_re, "candidates": table}
 
 
