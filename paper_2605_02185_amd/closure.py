@@ -211,21 +211,35 @@ def fit_and_select(X, T, bias, seeds=SEEDS, val_re=VAL_RE, d=40, u=0.05, collisi
                                     interval=sc["interval"], beta=sc["beta"], val_loss=hist[-1])
     res = evaluate(cands, d=d, u=u, re=val_re, collision=collision, start="cold", total=total,
                    stats_steps=stats_steps, log=log)
-    table, best, best_err = {}, None, float("inf")
-    for name, spec in cands.items():
-        err = res[name].get("rel_err")
-        ok = bool(err) and res[name]["diverged_step"] == 0
-        worst = max(err["mean_cd"], err["st"]) if ok else float("inf")
-        table[name] = {"val_loss": spec["val_loss"], "rel_err": err, "worst_cd_st": worst,
-                       "cl_ok": ok and err["cl_amp"] < CL_BOUND}
-    pool = [n for n in table if table[n]["cl_ok"]] or list(table)
-    for name in pool:
-        if table[name]["worst_cd_st"] < best_err:
-            best, best_err = name, table[name]["worst_cd_st"]
+    table = {name: {"val_loss": spec["val_loss"], "rel_err": res[name].get("rel_err"),
+                    "diverged_step": res[name]["diverged_step"]} for name, spec in cands.items()}
+    best, best_err = select(table)
     if best is None:
         raise RuntimeError("no candidate network ran stably in the closed loop")
     log(f"closure select: {best} (larger of the mean Cd and St errors {best_err:.4f} at Re {val_re:g})")
     return cands[best]["net"], cands[best]["norm"], {"chosen": best, "val_re": val_re, "candidates": table}
+
+
+def select(table, cl_bound=None):
+    """The selection rule of fit_and_select on its table ({name: {"rel_err":
+    {"mean_cd", "cl_amp", "st"} or None, "diverged_step"}}): among the stable
+    candidates whose lift amplitude error is below cl_bound (CL_BOUND by
+    default; all stable ones when none is), the one whose larger error of
+    mean Cd and St is smallest.  Adds "worst_cd_st" and "cl_ok" to each
+    entry; returns (name, its larger error), or (None, inf) when none ran
+    stably."""
+    cl_bound = CL_BOUND if cl_bound is None else cl_bound
+    for entry in table.values():
+        err = entry.get("rel_err")
+        ok = bool(err) and entry.get("diverged_step", 0) == 0
+        entry["worst_cd_st"] = max(err["mean_cd"], err["st"]) if ok else float("inf")
+        entry["cl_ok"] = ok and err["cl_amp"] < cl_bound
+    pool = [n for n in table if table[n]["cl_ok"]] or list(table)
+    best, best_err = None, float("inf")
+    for name in pool:
+        if table[name]["worst_cd_st"] < best_err:
+            best, best_err = name, table[name]["worst_cd_st"]
+    return best, best_err
 
 
 def _init_params(rng):

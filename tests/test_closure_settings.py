@@ -1,0 +1,47 @@
+"""Host-side settings of the learned closure's pipeline (no GPU): the
+settings carried to other diameters and the seed selection rule."""
+import math
+
+from paper_2605_02185_amd import closure as C
+
+
+def test_scaled_settings_at_d40_are_the_pipeline_constants():
+    sc = C.scaled(40)
+    assert sc["interval"] == C.INTERVAL and sc["beta"] == C.BETA and sc["guard"] == C.OUTLET_GUARD
+    assert (sc["spin_up"], sc["every"], sc["bias_every"], sc["total"], sc["stats"]) == (175000, 5, 25, 300000, 50000)
+    assert sc["taper"] == 80
+
+
+def test_scaled_settings_follow_the_flow_time_and_the_diameter():
+    sc = C.scaled(80)
+    assert (sc["spin_up"], sc["every"], sc["bias_every"], sc["total"], sc["stats"]) == (350000, 10, 50, 600000, 100000)
+    assert sc["taper"] == 160 and sc["guard"] == (C.OUTLET_GUARD[0], 80, C.OUTLET_GUARD[2])
+    # a whole number of three-step launches between evaluations, and a divisor of the 96-step ring
+    assert sc["interval"] % 3 == 0 and 96 % sc["interval"] == 0
+    # the low-pass time constant (interval / beta steps) doubles with D
+    assert math.isclose(sc["interval"] / sc["beta"], 2 * C.INTERVAL / C.BETA)
+
+
+def _table(rows):
+    return {name: {"rel_err": None if e is None else dict(zip(("mean_cd", "cl_amp", "st"), e)),
+                   "diverged_step": d} for name, (e, d) in rows.items()}
+
+
+def test_selection_prefers_mean_cd_and_st_among_bounded_lift_errors():
+    # the candidates of the D = 80 pipeline at Re = 120 (100k snapshots, 30 epochs)
+    t = _table({"seed7": ((0.0005, 0.097, 0.0094), 0), "seed8": ((0.0075, 0.041, 0.0069), 0),
+                "seed9": ((0.0042, 0.184, 0.0099), 0), "seed10": ((0.0138, 0.034, 0.0140), 0)})
+    assert C.select(t)[0] == "seed8"
+    # and those of D = 40: only seed 7 has its lift amplitude within 5 %
+    t = _table({"seed7": ((0.0044, 0.0002, 0.0066), 0), "seed8": ((0.0173, 0.115, 0.0111), 0),
+                "seed9": ((0.0031, 0.076, 0.0005), 0), "seed10": ((0.0040, 0.079, 0.0008), 0)})
+    assert C.select(t) == ("seed7", 0.0066)
+
+
+def test_selection_falls_back_to_every_stable_candidate_and_skips_diverged_ones():
+    t = _table({"a": ((0.002, 0.2, 0.003), 0), "b": ((0.001, 0.3, 0.002), 0), "c": ((0.0, 0.0, 0.0), 1200),
+                "d": (None, 0)})
+    best, err = C.select(t)
+    assert best == "b" and err == 0.002
+    assert not t["c"]["cl_ok"] and t["c"]["worst_cd_st"] == float("inf")
+    assert C.select(_table({"c": ((0.0, 0.0, 0.0), 7)})) == (None, float("inf"))

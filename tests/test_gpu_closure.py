@@ -255,6 +255,34 @@ def test_closure_interval_is_the_same_on_every_kernel_and_schedule(interval):
     assert not np.array_equal(plain.get_populations(np.float64), ref[0])  # the residuals act
 
 
+def test_residual_query_leaves_the_closed_loop_unchanged():
+    """lbm_closure_residuals evaluates the network into a buffer of its own:
+    querying it between steps of a closed-loop run (low-pass on, network
+    every 8 steps, queries in the middle of an interval, when the next
+    residuals are already computed but not yet in use) changes no bit of
+    the run."""
+    kw = _trunc()
+    runs = []
+    for query in (False, True):
+        lat = lbm.Lattice(lbm.make_params(**kw))
+        net = lbm.Mlp(random_params(21, last=0.02))
+        norm = np.concatenate([np.zeros(36), np.full(36, 20.0), np.full(3, 1e-4)]).astype(np.float32)
+        lat.enable_closure(net, norm, 7)
+        lat.set_closure_filter(0.5, 0)
+        lat.set_closure_interval(8)
+        for n in (13, 100, 19):
+            lat.step(n)
+            if query:
+                r = lat.closure_residuals()
+                assert np.isfinite(r).all() and np.abs(r).max() > 0.0
+        runs.append((lat.get_populations(np.float64), lat.forces()))
+        lat.close()
+    assert np.array_equal(runs[0][0], runs[1][0])
+    for a, b in zip(runs[0][1], runs[1][1]):
+        if a is not None:
+            assert np.array_equal(a, b)
+
+
 def test_closure_residuals_match_reference_network():
     kw = _trunc()
     lat = lbm.Lattice(lbm.make_params(**kw))
