@@ -280,7 +280,7 @@ lbm_status create_impl(const lbm_params* cases, const int64_t* budgets, int32_t 
     lbm::CaseArgs& c = b->hcase[k];
     c.g = b->hg[k].g;
     c.p = lbm::make_physics(&p);
-    const size_t fbytes = (size_t)9 * c.g.plane * sizeof(float);
+    const size_t fbytes = (size_t)lbm::state_floats(c.g) * sizeof(float);
     for (int j = 0; j < 2; ++j) {
       if ((st = dmalloc(b, (void**)&c.buf[j], fbytes)) != LBM_OK) return st;
       BTRY(hipMemsetAsync(c.buf[j], 0, fbytes, b->stream));

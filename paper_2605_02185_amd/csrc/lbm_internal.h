@@ -29,8 +29,11 @@ constexpr uint16_t kSolid = 1;
 
 struct Geometry {
   int nx, ny;
-  int pitch;        // floats per row (>= nx, multiple of 64)
-  int64_t plane;    // floats per population plane (>= ny * pitch)
+  // population k of node (x, y) is at k * plane + y * pitch + x; the host
+  // interleaves rows (plane = one row padded to a multiple of 64 floats,
+  // pitch = 9 * plane), the kernels only use the two strides
+  int pitch;        // floats from one row to the next (multiple of 64)
+  int64_t plane;    // floats from one population to the next (multiple of 64)
   // cylinder rectangle [rx0, rx0+rw) x [ry0, ry0+rh) holding all solid nodes
   // and all their fluid neighbours; empty (rw = rh = 0) without a cylinder
   int rx0, ry0, rw, rh;
@@ -45,6 +48,9 @@ struct Geometry {
   // -c_k ends in the solid); null with half-way bounce-back
   const float* q;
 };
+
+// Floats of one state buffer: the last population's last row ends there.
+inline int64_t state_floats(const Geometry& g) { return 8 * g.plane + (int64_t)g.ny * g.pitch; }
 
 struct Physics {
   float omega;     // 1/tau

@@ -1,7 +1,9 @@
 // gfx950 kernels of the D2Q9 lattice Boltzmann cylinder-flow solver (arXiv 2605.02185).
 //
-// State between steps: post-collision populations f*(x, t) in 9 SoA planes,
-// rows padded to a multiple of 64 floats, stored shifted by the rest
+// State between steps: post-collision populations f*(x, t), each row of the
+// lattice holding the nine populations' rows one after another (structure of
+// arrays within a row), rows padded to a multiple of 64 floats, stored
+// shifted by the rest
 // equilibrium as h_k = f*_k - w_k (FP32).  The deviations are two orders of
 // magnitude smaller than f itself, so FP32 rounding errors shrink by the same
 // factor (shifted storage, Skordos 1993).  Every population formula of the
@@ -1581,6 +1583,9 @@ constexpr Variant kVariants[] = {
     {"t4_h24u_s8", kStrip4, 24, 1, 0, 0, 4, 8, 0, 2},
     {"t3_h16u_s2", kStrip3, 16, 1, 0, 0, 3, 2, 0, 2},
     {"t4_h16u_s2", kStrip4, 16, 1, 0, 0, 4, 2, 0, 2},
+    {"t4_h12u_s6", kStrip4, 12, 1, 0, 0, 4, 6, 0, 2},
+    {"t4_h10u_s10", kStrip4, 10, 1, 0, 0, 4, 10, 0, 2},
+    {"t4_h14u_s14", kStrip4, 14, 1, 0, 0, 4, 14, 0, 2},
 };
 
 }  // namespace
@@ -1604,11 +1609,13 @@ const Variant& variant(int v) { return kVariants[v - 1]; }
 // 22 M, against 165 k, 191 k and 209 k with 8-row segments holding their
 // outputs; one step per launch gives 82 k at 22 M).  Longer
 // boundary pieces recompute fewer rows but lengthen the serial chain of each
-// boundary wave, which only long launches hide: from 2^24 nodes 12-row
-// segments with 12-row pieces are about 1 % faster (397-400 against 401-403
-// us per launch at 22 M), and up to 8 % slower on the slab.
+// boundary wave, which only long launches hide.  On the row-interleaved
+// state, from 2^22 nodes 10-row segments with 10-row pieces win (233 k MLUPS
+// at 22 M, tied with 12-row ones, against 223 k for 16-row segments with
+// 8-row pieces; 199 k against 194 k and 191 k at 5.5 M) and 16-row segments
+// with 8-row pieces below (181 k against 174 k for 12 rows on the 2.8 M slab).
 int default_variant(int64_t nodes) {
-  const char* want = nodes >= ((int64_t)1 << 24)   ? "t4_h12u_s12"
+  const char* want = nodes >= ((int64_t)1 << 22)   ? "t4_h10u_s10"
                      : nodes >= ((int64_t)1 << 21) ? "t4_h16u_s8"
                      : nodes >= ((int64_t)1 << 20) ? "t3_h16u_s2"
                      : nodes >= ((int64_t)1 << 18) ? "t2_h4_u1"
@@ -1737,6 +1744,9 @@ hipError_t launch_step(const StepArgs& a, int v, hipStream_t s) {
     LBM_TN(false, 24, 8, 4, 2)
     LBM_TN(false, 16, 2, 3, 2)
     LBM_TN(false, 16, 2, 4, 2)
+    LBM_TN(false, 12, 6, 4, 2)
+    LBM_TN(false, 10, 10, 4, 2)
+    LBM_TN(false, 14, 14, 4, 2)
 #undef LBM_TN
     return hipErrorInvalidValue;
   }
