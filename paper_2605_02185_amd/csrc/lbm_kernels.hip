@@ -1610,13 +1610,12 @@ const Variant& variant(int v) { return kVariants[v - 1]; }
 // outputs; one step per launch gives 82 k at 22 M).  Longer
 // boundary pieces recompute fewer rows but lengthen the serial chain of each
 // boundary wave, which only long launches hide.  On the row-interleaved
-// state, from 2^22 nodes 10-row segments with 10-row pieces win (233 k MLUPS
+// state 10-row segments with 10-row pieces win from 2^21 nodes (233 k MLUPS
 // at 22 M, tied with 12-row ones, against 223 k for 16-row segments with
-// 8-row pieces; 199 k against 194 k and 191 k at 5.5 M) and 16-row segments
-// with 8-row pieces below (181 k against 174 k for 12 rows on the 2.8 M slab).
+// 8-row pieces; 199 k against 194 k and 191 k at 5.5 M; 188 k against 183 k
+// on the 2.8 M slab).
 int default_variant(int64_t nodes) {
-  const char* want = nodes >= ((int64_t)1 << 22)   ? "t4_h10u_s10"
-                     : nodes >= ((int64_t)1 << 21) ? "t4_h16u_s8"
+  const char* want = nodes >= ((int64_t)1 << 21)   ? "t4_h10u_s10"
                      : nodes >= ((int64_t)1 << 20) ? "t3_h16u_s2"
                      : nodes >= ((int64_t)1 << 18) ? "t2_h4_u1"
                                                    : "v1_ty1_xcd";
