@@ -1586,6 +1586,8 @@ constexpr Variant kVariants[] = {
     {"t4_h12u_s6", kStrip4, 12, 1, 0, 0, 4, 6, 0, 2},
     {"t4_h10u_s10", kStrip4, 10, 1, 0, 0, 4, 10, 0, 2},
     {"t4_h14u_s14", kStrip4, 14, 1, 0, 0, 4, 14, 0, 2},
+    {"t3_h10u_s2", kStrip3, 10, 1, 0, 0, 3, 2, 0, 2},
+    {"t3_h12u_s2", kStrip3, 12, 1, 0, 0, 3, 2, 0, 2},
 };
 
 }  // namespace
@@ -1746,6 +1748,8 @@ hipError_t launch_step(const StepArgs& a, int v, hipStream_t s) {
     LBM_TN(false, 12, 6, 4, 2)
     LBM_TN(false, 10, 10, 4, 2)
     LBM_TN(false, 14, 14, 4, 2)
+    LBM_TN(false, 10, 2, 3, 2)
+    LBM_TN(false, 12, 2, 3, 2)
 #undef LBM_TN
     return hipErrorInvalidValue;
   }
