@@ -199,7 +199,7 @@ lbm_status lbm_shedding_stats(const double* cd, const double* cl, int64_t n, dou
  * closure evaluations that do not fill a launch) run the one-step kernel.
  * The default of a new context is "t4_h10u_s10" from 2^21 nodes,
  * "t3_h16u_s2"
- * from 2^20, "t2_h4_u1" from 2^18 and the one-step "v1_ty1_xcd" (cached
+ * from 2^20, "t2_h8_u1" from 2^18 and the one-step "v1_ty1_xcd" (cached
  * stores, each XCD on its own band of rows) below ("_hH": interior segments
  * of H rows, "_hHu": whose output rows are stored as they are made; "_sN":
  * segments that need the boundary code run in pieces of N rows; "_uN":

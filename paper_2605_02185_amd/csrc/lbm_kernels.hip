@@ -1588,6 +1588,8 @@ constexpr Variant kVariants[] = {
     {"t4_h14u_s14", kStrip4, 14, 1, 0, 0, 4, 14, 0, 2},
     {"t3_h10u_s2", kStrip3, 10, 1, 0, 0, 3, 2, 0, 2},
     {"t3_h12u_s2", kStrip3, 12, 1, 0, 0, 3, 2, 0, 2},
+    {"t2_h6_u1", kStrip2, 6, 1, 0, 0, 2, 1, 1},
+    {"t2_h8_u1", kStrip2, 8, 1, 0, 0, 2, 1, 1},
 };
 
 }  // namespace
@@ -1615,11 +1617,14 @@ const Variant& variant(int v) { return kVariants[v - 1]; }
 // state 10-row segments with 10-row pieces win from 2^21 nodes (233 k MLUPS
 // at 22 M, tied with 12-row ones, against 223 k for 16-row segments with
 // 8-row pieces; 199 k against 194 k and 191 k at 5.5 M; 188 k against 183 k
-// on the 2.8 M slab).
+// on the 2.8 M slab).  For two steps the row-interleaved state favours 8-row
+// interior segments with the same one-row boundary pieces (6.0 against 6.3 us
+// per step on the 458 k-node closure window, 5.5 against 5.9 at 320 k; 12 and
+// 16 rows lose).
 int default_variant(int64_t nodes) {
   const char* want = nodes >= ((int64_t)1 << 21)   ? "t4_h10u_s10"
                      : nodes >= ((int64_t)1 << 20) ? "t3_h16u_s2"
-                     : nodes >= ((int64_t)1 << 18) ? "t2_h4_u1"
+                     : nodes >= ((int64_t)1 << 18) ? "t2_h8_u1"
                                                    : "v1_ty1_xcd";
   for (int v = 1; v <= num_variants(); ++v)
     if (std::strcmp(kVariants[v - 1].name, want) == 0) return v;
@@ -1712,6 +1717,8 @@ hipError_t launch_step(const StepArgs& a, int v, hipStream_t s) {
     LBM_T2(false, 4, 4, 0)
     LBM_T2(false, 6, 4, 0)
     LBM_T2(false, 4, 1, 1)
+    LBM_T2(false, 6, 1, 1)
+    LBM_T2(false, 8, 1, 1)
 #undef LBM_T2
     return hipErrorInvalidValue;
   }

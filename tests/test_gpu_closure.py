@@ -238,11 +238,11 @@ def test_closure_interval_is_the_same_on_every_kernel_and_schedule(interval):
     kw = _trunc()
     by_name = {lbm.variant_name(v): v for v in range(1, lbm.num_variants() + 1)}
     t2, t3, t4 = by_name["t2_h4"], by_name["t3_h8_s2"], by_name["t4_h8_s8"]
-    u2, t4u = by_name["t2_h4_u1"], by_name["t4_h16u_s8"]
+    u2, u8, t4u = by_name["t2_h4_u1"], by_name["t2_h8_u1"], by_name["t4_h16u_s8"]
     ref = _closure_run(kw, 1, interval, False, [131])
     for variant, graphs, calls in ((t2, False, [131]), (t2, True, [131]), (t2, True, [3, 64, 1, 63]),
                                    (1, True, [70, 61]), (t4, True, [131]), (t4, False, [5, 126]),
-                                   (t3, True, [131]), (t3, False, [7, 124]), (u2, True, [131]),
+                                   (t3, True, [131]), (t3, False, [7, 124]), (u2, True, [131]), (u8, True, [131]),
                                    (t4u, True, [131])):
         got = _closure_run(kw, variant, interval, graphs, calls)
         note(f"  interval {interval} variant {lbm.variant_name(variant)} graphs {graphs} calls {calls}")

@@ -316,7 +316,8 @@ def test_tall_segment_variants_match_one_step_bitwise(name):
 
 def test_default_variant_follows_the_lattice_size():
     """One step per launch below 2^18 nodes (cached stores, XCD bands), two
-    from 2^18 (one-row boundary pieces loading all their rows first), three
+    from 2^18 (8-row segments, one-row boundary pieces loading all their
+    rows first), three
     from 2^20 (2-row pieces), four from 2^21 (10-row interior segments
     storing rows as they are made, 10-row boundary pieces); variant 0
     restores the default."""
@@ -324,7 +325,7 @@ def test_default_variant_follows_the_lattice_size():
     big = lbm.Lattice(lbm.make_params(**WORKLOADS["cyl_d40"]))
     assert lbm.variant_name(small.variant) == "v1_ty1_xcd"
     assert lbm.variant_name(big.variant) == "t3_h16u_s2"
-    for name, want in (("cyl_d20_mrt", "t2_h4_u1"), ("slab_d160_of8", "t4_h10u_s10"), ("cyl_d80", "t4_h10u_s10"),
+    for name, want in (("cyl_d20_mrt", "t2_h8_u1"), ("slab_d160_of8", "t4_h10u_s10"), ("cyl_d80", "t4_h10u_s10"),
                        ("cyl_d160", "t4_h10u_s10")):
         lat = lbm.Lattice(lbm.make_params(**WORKLOADS[name]))
         assert lbm.variant_name(lat.variant) == want, name
