@@ -280,7 +280,8 @@ int32_t lbm_batch_variant(const lbm_batch* b);
 /* Select the ensemble's kernel variant (synchronises the ensemble's stream;
  * also done by the autotuner).  Allowed: the one-step variants without a
  * remapped block order, and the multi-step variants "t3_h8_s2", "t3_h8_s4",
- * "t4_h8_s2", "t4_h8_s4", "t4_h8_s8", "t4_h16u_s8" and "t3_h16u_s2", which
+ * "t4_h8_s2", "t4_h8_s4", "t4_h8_s8", "t4_h16u_s8", "t4_h10u_s10" and
+ * "t3_h16u_s2", which
  * advance every active case by
  * their 3 or 4 steps per launch (the steps a case has left before the active
  * set changes, when fewer, run one per launch on "v1_ty1_nt").  Every

@@ -1652,7 +1652,7 @@ hipError_t launch_step_batch(const CaseArgs* cases, const int2* tiles, int ntile
 
 // Multi-step variants the ensemble runs (instantiated below).
 #define LBM_TB_LIST(X) X(8, 2, 3, 0) X(8, 4, 3, 0) X(8, 2, 4, 0) X(8, 4, 4, 0) X(8, 8, 4, 0) X(16, 8, 4, 2) \
-  X(16, 2, 3, 2)
+  X(16, 2, 3, 2) X(10, 10, 4, 2)
 
 bool multistep_batch_supported(int v) {
   if (v < 1 || v > num_variants()) return false;

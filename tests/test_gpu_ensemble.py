@@ -54,7 +54,7 @@ def test_mixed_ensemble_matches_separate_runs_bitwise():
             assert np.array_equal(a, c), i
 
 
-MULTI = ["t3_h8_s2", "t3_h8_s4", "t4_h8_s2", "t4_h8_s4", "t4_h8_s8", "t4_h16u_s8", "t3_h16u_s2"]
+MULTI = ["t3_h8_s2", "t3_h8_s4", "t4_h8_s2", "t4_h8_s4", "t4_h8_s8", "t4_h16u_s8", "t4_h10u_s10", "t3_h16u_s2"]
 
 
 @pytest.mark.parametrize("name", MULTI)
