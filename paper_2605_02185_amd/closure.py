@@ -66,15 +66,20 @@ VAL_RE = 120.0
 CL_BOUND = 0.05
 
 
-def scaled(d=40):
+def scaled(d=40, interval=None):
     """The D = 40 settings carried to diameter d (U fixed): step counts scale
     with the flow time D/U, the rows' plain taper and the outlet guard's with
     D.  Above D = 40 the window is large enough for three-step launches, so
     the network is evaluated every 12 steps (a whole number of them), with
     the low-pass's time constant (interval / beta steps) scaled with D.  At
-    d = 40 this is exactly the settings above."""
+    d = 40 this is exactly the settings above.  An explicit `interval` keeps
+    the same time constant (beta grows with it): fewer evaluations, a
+    coarser-grained low-pass."""
     f = d / 40.0
-    interval = INTERVAL if d <= 40 else 12
+    if interval is None:
+        interval = INTERVAL if d <= 40 else 12
+    if interval < 1:
+        raise ValueError("interval must be at least one step")
     return dict(spin_up=int(round(175000 * f)), every=max(1, int(round(5 * f))),
                 bias_every=max(1, int(round(25 * f))), total=int(round(300000 * f)),
                 stats=int(round(50000 * f)), interval=interval, beta=min(1.0, BETA * interval / (INTERVAL * f)),
@@ -195,13 +200,14 @@ def fit(X, T, epochs=30, batch=4096, lr=1e-3, seed=7, val_frac=0.05, init=None, 
 
 
 def fit_and_select(X, T, bias, seeds=SEEDS, val_re=VAL_RE, d=40, u=0.05, collision=None, epochs=20, noise=NOISE,
-                   total=None, stats_steps=None, log=print):
+                   total=None, stats_steps=None, interval=None, log=print):
     """One network per seed (fit), each run in the closed loop (rows and
-    guarded outlet, cold start) at Re = val_re against the full domain at
-    that Re; returns (network, norm, table) for the seed whose larger
-    relative error of mean Cd and St is smallest among those whose lift
-    amplitude error is below CL_BOUND (all seeds when none is)."""
-    sc = scaled(d)
+    guarded outlet, cold start, evaluated as scaled(d, interval) says) at
+    Re = val_re against the full domain at that Re; returns (network, norm,
+    table) for the seed whose larger relative error of mean Cd and St is
+    smallest among those whose lift amplitude error is below CL_BOUND (all
+    seeds when none is)."""
+    sc = scaled(d, interval)
     total = sc["total"] if total is None else total
     stats_steps = sc["stats"] if stats_steps is None else stats_steps
     cands = {}
@@ -356,19 +362,21 @@ def main(argv=None):
     ap.add_argument("--total", type=int, default=None, help="steps per run (default: 300k at D = 40, scaled with D)")
     ap.add_argument("--stats", type=int, default=None, help="steps of statistics (default: 50k at D = 40, scaled)")
     ap.add_argument("--bgk", action="store_true", help="BGK instead of the bulk-damped MRT collision")
+    ap.add_argument("--interval", type=int, default=None,
+                    help="steps between network evaluations (default: 8 up to D = 40, 12 above)")
     ap.add_argument("--save", default=None, help="write the trained weights and norm (.npz)")
     args = ap.parse_args(argv)
     import torch
 
     torch.cuda.set_device(0)
     coll = None if args.bgk else damped_mrt()
-    sc = scaled(args.d)
+    sc = scaled(args.d, args.interval)
     total = sc["total"] if args.total is None else args.total
     stats = sc["stats"] if args.stats is None else args.stats
     X, T, bias = generate(d=args.d, snapshots=args.snapshots, collision=coll, bias_snapshots=BIAS_SNAPSHOTS,
                           spin_up=sc["spin_up"], every=sc["every"], bias_every=sc["bias_every"])
     net, norm, sel = fit_and_select(X, T, bias, d=args.d, collision=coll, epochs=args.epochs, noise=args.noise,
-                                    total=total, stats_steps=stats)
+                                    total=total, stats_steps=stats, interval=args.interval)
     if args.save:
         np.savez(args.save, params=net.get_params(), norm=norm, bias=bias)
     nets = {"trunc_rows_outlet": dict(net=net, norm=norm, mask=7, taper=sc["taper"], guard=sc["guard"], bias=bias,

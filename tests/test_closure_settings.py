@@ -45,3 +45,20 @@ def test_selection_falls_back_to_every_stable_candidate_and_skips_diverged_ones(
     assert best == "b" and err == 0.002
     assert not t["c"]["cl_ok"] and t["c"]["worst_cd_st"] == float("inf")
     assert C.select(_table({"c": ((0.0, 0.0, 0.0), 7)})) == (None, float("inf"))
+
+
+def test_an_explicit_interval_keeps_the_low_pass_time_constant():
+    base = C.scaled(40)
+    sc = C.scaled(40, 16)
+    assert sc["interval"] == 16 and math.isclose(sc["beta"], 2 * C.BETA)
+    assert math.isclose(sc["interval"] / sc["beta"], base["interval"] / base["beta"])
+    assert {k: v for k, v in sc.items() if k not in ("interval", "beta")} == \
+        {k: v for k, v in base.items() if k not in ("interval", "beta")}
+    # a time constant shorter than the interval saturates at a plain replacement
+    assert C.scaled(40, 200)["beta"] == 1.0
+    try:
+        C.scaled(40, 0)
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("interval 0 accepted")
