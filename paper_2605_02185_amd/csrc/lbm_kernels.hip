@@ -93,18 +93,35 @@ __device__ __forceinline__ void collide_bgk(const float (&g)[9], float drho, flo
 //   p_xx: M_pxx g - rho (u_x^2 - u_y^2)  p_xy: M_pxy g - rho u_x u_y
 // with m_eq = rho (-2 + 3 u.u, 1 - 3 u.u, u_x, -u_x, u_y, -u_y,
 // u_x^2 - u_y^2, u_x u_y), the equilibrium moments of Eq. 3.
-__device__ __forceinline__ void collide_mrt(const float (&g)[9], float drho, float rho, float ux, float uy,
-                                            float jx, float jy, const Physics& p, float (&out)[9]) {
+//
+// All moments come from eight sums and differences of opposite pairs
+// (a13 = g1 + g3, d13 = g1 - g3, ...): rho - 1 = g0 + s14 + s58,
+// j_x = d13 + (d57 + d86), j_y = d24 + (d57 - d86), M_qx g = -2 d13 + (d57 +
+// d86), M_qy g = -2 d24 + (d57 - d86), M_pxx g = a13 - a24, M_pxy g = a57 -
+// a68, with s14 = a13 + a24 and s58 = a57 + a68 in M_e g and M_eps g.  The
+// node's moments and the density check are done here (collide_t calls it
+// for MRT before computing the BGK path's own sums).
+__device__ __forceinline__ void collide_mrt(const float (&g)[9], const Physics& p, float (&out)[9], bool& bad) {
 #pragma clang fp contract(off)
-  const float s14 = (g[1] + g[2]) + (g[3] + g[4]);
-  const float s58 = (g[5] + g[6]) + (g[7] + g[8]);
+  const float a13 = g[1] + g[3], a24 = g[2] + g[4], a57 = g[5] + g[7], a68 = g[6] + g[8];
+  const float d13 = g[1] - g[3], d24 = g[2] - g[4], d57 = g[5] - g[7], d86 = g[8] - g[6];
+  const float s14 = a13 + a24, s58 = a57 + a68;
+  const float e = d57 + d86, f = d57 - d86;
+  const float drho = (g[0] + s14) + s58;
+  const float rho = 1.0f + drho;
+  const float ir = __builtin_amdgcn_rcpf(rho);
+  const float jx = d13 + e;
+  const float jy = d24 + f;
+  const float ux = jx * ir;
+  const float uy = jy * ir;
+  bad |= !(rho > 0.0f && rho < 10.0f);
   const float ru2 = rho * __fmaf_rn(ux, ux, uy * uy);
   const float me = __fmaf_rn(2.0f, s58, __fmaf_rn(-4.0f, g[0], -s14));
   const float meps = __fmaf_rn(-2.0f, s14, __fmaf_rn(4.0f, g[0], s58));
-  const float mqx = __fmaf_rn(-2.0f, g[1] - g[3], (g[5] - g[6]) + (g[8] - g[7]));
-  const float mqy = __fmaf_rn(-2.0f, g[2] - g[4], (g[5] + g[6]) - (g[7] + g[8]));
-  const float mpxx = (g[1] + g[3]) - (g[2] + g[4]);
-  const float mpxy = (g[5] - g[6]) + (g[7] - g[8]);
+  const float mqx = __fmaf_rn(-2.0f, d13, e);
+  const float mqy = __fmaf_rn(-2.0f, d24, f);
+  const float mpxx = a13 - a24;
+  const float mpxy = a57 - a68;
   const float a1 = p.s_e * (1.0f / 36.0f) * __fmaf_rn(-3.0f, ru2, __fmaf_rn(2.0f, drho, me));
   const float a2 = p.s_eps * (1.0f / 36.0f) * __fmaf_rn(3.0f, ru2, meps - drho);
   const float a4 = p.s_qx * (1.0f / 12.0f) * (mqx + jx);
@@ -134,6 +151,10 @@ enum : int { kBgk = 0, kMrt = 1, kEither = 2 };
 template <int COLL>
 __device__ __forceinline__ void collide_t(const float (&g)[9], const Physics& p, float (&out)[9], bool& bad) {
 #pragma clang fp contract(off)
+  if (COLL == kMrt || (COLL == kEither && p.mrt)) {
+    collide_mrt(g, p, out, bad);
+    return;
+  }
   const float drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
   const float rho = 1.0f + drho;
   const float ir = __builtin_amdgcn_rcpf(rho);
@@ -142,10 +163,7 @@ __device__ __forceinline__ void collide_t(const float (&g)[9], const Physics& p,
   const float ux = jx * ir;
   const float uy = jy * ir;
   bad |= !(rho > 0.0f && rho < 10.0f);
-  if (COLL == kMrt || (COLL == kEither && p.mrt))
-    collide_mrt(g, drho, rho, ux, uy, jx, jy, p, out);
-  else
-    collide_bgk(g, drho, rho, ux, uy, p.omega, out);
+  collide_bgk(g, drho, rho, ux, uy, p.omega, out);
 }
 
 __device__ __forceinline__ void collide(const float (&g)[9], const Physics& p, float (&out)[9], bool& bad) {
