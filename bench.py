@@ -351,7 +351,7 @@ def ensemble_result(torch, lbm, steps: int = 1920) -> dict:
 def closure_result() -> dict:
     """Learned closure at D = 40 with the bulk-damped MRT collision: data
     from full-domain runs (Re 80, 100, 120; per-node mean residual and random
-    samples), four networks trained, the one closest to the full domain in
+    samples), eight networks trained, the one closest to the full domain in
     the closed loop at the held-out Re = 120 kept; then at Re = 100 the full
     domain against the truncated window (plain, and learned top, bottom and
     guarded outlet), every run 300k steps from the initial state, statistics

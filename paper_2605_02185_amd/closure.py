@@ -57,8 +57,10 @@ BIAS_SNAPSHOTS = 3000
 # most, the lift amplitude within 1.6-14 %.  fit_and_select trains one
 # network per seed and keeps the one whose closed-loop window comes closest
 # to the full domain at a held-out Reynolds number (VAL_RE, one of the
-# training runs' but not the one reported).
-SEEDS = (7, 8, 9, 10)
+# training runs' but not the one reported).  Eight seeds: with four, often
+# only one passed the lift bound below at the held-out Re, and the rule then
+# had nothing to choose from.
+SEEDS = tuple(range(7, 15))
 VAL_RE = 120.0
 # Seeds whose lift amplitude at the held-out Re is off by more than this are
 # passed over: among the rest the one closest in mean Cd and St is kept (the

@@ -356,8 +356,8 @@ def test_closure_residuals_enter_the_missing_populations():
 def test_trained_closure_versus_plain_truncation_from_a_cold_start():
     """End to end at D = 40 with the bulk-damped MRT collision: data from
     full-domain runs at Re 80/100/120 (per-node mean residual plus random
-    samples of the fluctuations), four networks trained on the GPU (seeds
-    7-10), the one whose closed loop comes closest to the full domain at the
+    samples of the fluctuations), eight networks trained on the GPU (seeds
+    7-14), the one whose closed loop comes closest to the full domain at the
     held-out Re = 120 kept; then, at Re = 100, the full domain and the
     26 D x 11 D window (learned top, bottom and guarded outlet) each run 300k
     steps from the initial state, statistics over the last 50k (about 10
