@@ -67,6 +67,45 @@ def stored_counters(workload: str, collision: str, variant: str):
     return d
 
 
+def roofline(nodes: int, steps_per_launch: int, launch_s: float, counters) -> dict:
+    """The bench line's roofline object for a launch of `steps_per_launch`
+    steps over `nodes` nodes lasting `launch_s` seconds, with the stored
+    counter summary `counters` (stored_counters) or None."""
+    floor_bytes = BYTES_PER_NODE * nodes  # one read and one write of the state per launch
+    effective = BYTES_PER_NODE * nodes * steps_per_launch / launch_s / 1e9
+    floor_rate = floor_bytes / launch_s / 1e9
+    traffic = counters.get("bytes_per_launch") if counters else None
+    valu = counters.get("valu") if counters else None
+    achieved = traffic / launch_s / 1e9 if traffic else None
+    roof = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1) if achieved else None,
+        "peak": PEAK_HBM_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / PEAK_HBM_GBS, 4) if achieved else None,
+        "traffic": traffic,
+        "kernel": {1: "step_kernel", 2: "step2_kernel"}.get(steps_per_launch, "multistep_kernel"),
+        "steps_per_launch": steps_per_launch,
+        "launch_us": round(launch_s * 1e6, 2),
+        "floor_bytes_per_launch": floor_bytes,
+        "frac_of_floor": round(floor_rate / PEAK_HBM_GBS, 4),
+        "traffic_over_floor": round(traffic / floor_bytes, 4) if traffic else None,
+        "effective_GBs": round(effective, 1),
+        "counters": ("profiles/traffic_step_kernel.json (kernel source " + counters["kernel_sha256_16"] + ")"
+                     if counters else "stale: taken on another kernel source or configuration"),
+    }
+    if valu:
+        # the vector ALU side of the same kernel, from the stored counters:
+        # FP32 operations per launch over the live launch time, against the
+        # 78.6 TFLOP/s of unpacked FP32 FMAs (256 CUs x 4 SIMDs x 16 lanes x
+        # 2 x 2.4 GHz; the packed forms behind the 157.3 figure are not used)
+        flops = valu["fp32_flop_per_launch"] / launch_s / 1e12
+        roof["valu"] = {"busy_pct": valu["valu_busy_pct"], "fp32_TFLOPs": round(flops, 2),
+                        "fp32_peak_TFLOPs": 78.6, "frac": round(flops / 78.6, 4),
+                        "insts_per_update": valu["valu_insts_per_update"]}
+    return roof
+
+
 def copy_ceiling(torch, lbm, nbytes: int, reps: int = 20) -> float:
     """GB/s of the library's plain streaming copy of nbytes (read + write
     counted): the bandwidth a kernel with perfect access patterns reaches."""
@@ -219,39 +258,8 @@ def main():
     vname = lbm.variant_name(lat.variant)
     steps_per_launch = {"t2": 2, "t3": 3, "t4": 4}.get(vname[:2], 1)
     launch_s = ms_per_step * steps_per_launch * 1e-3
-    floor_bytes = BYTES_PER_NODE * nodes  # one read and one write of the state per launch
-    effective = BYTES_PER_NODE * nodes * steps_per_launch / launch_s / 1e9
-    floor_rate = floor_bytes / launch_s / 1e9
-    counters = stored_counters(args.workload, args.collision, vname)
-    traffic = counters.get("bytes_per_launch") if counters else None
-    valu = counters.get("valu") if counters else None
-    achieved = traffic / launch_s / 1e9 if traffic else None
-    roof = {
-        "bound": "hbm",
-        "achieved": round(achieved, 1) if achieved else None,
-        "peak": PEAK_HBM_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / PEAK_HBM_GBS, 4) if achieved else None,
-        "traffic": traffic,
-        "kernel": {1: "step_kernel", 2: "step2_kernel"}.get(steps_per_launch, "multistep_kernel"),
-        "steps_per_launch": steps_per_launch,
-        "launch_us": round(launch_s * 1e6, 2),
-        "floor_bytes_per_launch": floor_bytes,
-        "frac_of_floor": round(floor_rate / PEAK_HBM_GBS, 4),
-        "traffic_over_floor": round(traffic / floor_bytes, 4) if traffic else None,
-        "effective_GBs": round(effective, 1),
-        "counters": ("profiles/traffic_step_kernel.json (kernel source " + counters["kernel_sha256_16"] + ")"
-                     if counters else "stale: taken on another kernel source or configuration"),
-    }
-    if valu:
-        # the vector ALU side of the same kernel, from the stored counters:
-        # FP32 operations per launch over the live launch time, against the
-        # 78.6 TFLOP/s of unpacked FP32 FMAs (256 CUs x 4 SIMDs x 16 lanes x
-        # 2 x 2.4 GHz; the packed forms behind the 157.3 figure are not used)
-        flops = valu["fp32_flop_per_launch"] / launch_s / 1e12
-        roof["valu"] = {"busy_pct": valu["valu_busy_pct"], "fp32_TFLOPs": round(flops, 2),
-                        "fp32_peak_TFLOPs": 78.6, "frac": round(flops / 78.6, 4),
-                        "insts_per_update": valu["valu_insts_per_update"]}
+    roof = roofline(nodes, steps_per_launch, launch_s, stored_counters(args.workload, args.collision, vname))
+    achieved = roof["achieved"]
     walls = {lbm.WALL_FREE_SLIP: "free-slip", lbm.WALL_PERIODIC: "periodic", lbm.WALL_NEBB: "nebb",
              lbm.WALL_MOVING_BB: "moving-bb"}
     out = {
