@@ -1,6 +1,6 @@
 """Host-side measurement code (no GPU): the bench line's roofline object,
-the gate on the committed counter summary, and the counter scaling of
-bench_traffic.py."""
+the gate on the committed counter summary, the counter scaling of
+bench_traffic.py and the bench's FP64 oracle baseline."""
 import csv
 import json
 import math
@@ -112,3 +112,23 @@ def test_bench_traffic_scales_each_counter_by_the_copy_of_known_size(tmp_path):
     assert d["dispatches"] == [3, 3] and d["steps_per_launch"] == 4 and d["kernel"] == "multistep_kernel"
     assert d["state_bytes_per_launch"] == 72 * nodes and d["algorithmic_bytes_per_launch"] == 4 * 72 * nodes
     assert d["kernel_sha256_16"] == bench.kernel_hash()
+
+
+def test_cpu_baseline_times_the_oracle_on_this_host(tmp_path, monkeypatch):
+    """The bench's cpu_baseline leg on a small lattice with a short budget:
+    the oracle built natively into a temporary library (removed afterwards),
+    the head figure on every OpenMP thread, and the D = 10, 40, 80 samples on
+    one thread and on all of them."""
+    import tempfile
+
+    from lbm_inputs import WORKLOADS
+
+    monkeypatch.setattr(tempfile, "gettempdir", lambda: str(tmp_path))
+    c = bench.cpu_baseline(dict(WORKLOADS["cyl_d10"]), budget_s=1.0)
+    assert c["kind"] == "oracle" and c["unit"] == "MLUPS" and c["bytes_per_update"] == 144
+    assert c["cores"] >= 1 and c["value"] > 0 and "410x210" in c["sample"]
+    assert [(s["workload"], s["threads"]) for s in c["samples"]] == [
+        (n, t) for n in ("cyl_d10", "cyl_d40", "cyl_d80") for t in (1, c["cores"])]
+    assert all(s["steps"] >= 1 and s["mlups"] > 0 for s in c["samples"])
+    assert c["build"].startswith("gcc ") and "-O3" in c["build"]
+    assert not list(tmp_path.glob("liblbm_oracle_native_*"))
