@@ -112,6 +112,16 @@ def test_geometry_matches_the_oracle_digitiser(D):
         assert (ns, nb, nl) == (1257, 168, 392)
 
 
+def test_splitmix64_matches_its_published_sequence():
+    """SplitMix64 (Steele, Lea & Flood 2014) seeded with 0 begins with the
+    outputs of its reference implementation."""
+    from lbm_inputs import splitmix64
+
+    g = splitmix64(0)
+    assert [next(g) for _ in range(4)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                          0x06C45D188009454F, 0xF88BB8A8724C81EC]
+
+
 def test_truncated_window_and_ensemble_are_valid():
     lbm.validate(lbm.make_params(**truncated_window()))
     cases = ensemble()
