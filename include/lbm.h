@@ -331,7 +331,13 @@ lbm_status lbm_mlp_set_norm(lbm_mlp* m, const float* norm);
 /* Training-input noise: train steps add independent N(0, amplitude^2) noise
  * to every z-scored input (counter-based SplitMix64 + Box-Muller, keyed by
  * seed, step, row and feature).  0 (the default) switches it off; gradients
- * from lbm_mlp_gradient never use it. */
+ * from lbm_mlp_gradient never use it.  Definition: the k-th train step
+ * (k = 0, 1, ... since lbm_mlp_create) has key K = seed * 0x100000001B3 + k
+ * (mod 2^64); feature c of dataset row i draws r = SplitMix64's output for
+ * the state K ^ (64 i + c) (Steele, Lea & Flood 2014: add 0x9E3779B97F4A7C15,
+ * then the two xor-shift-multiply rounds), u1 = ((r >> 40) + 1) / (2^24 + 1),
+ * u2 = ((r >> 16) mod 2^24) / 2^24, and the variate sqrt(-2 ln u1) cos(2 pi
+ * u2) (Box & Muller 1958), evaluated in FP32. */
 lbm_status lbm_mlp_set_noise(lbm_mlp* m, float amplitude, uint64_t seed);
 
 /* y[M][3] = network(x[M][36]); device pointers. */

@@ -92,6 +92,35 @@ def grad(flat, x, t, bf16_operands=True):
     return float(np.mean((y - t) ** 2)), pack(g)
 
 
+def splitmix64_output(state):
+    """SplitMix64 (Steele, Lea & Flood 2014): the output of the generator
+    whose state is `state` (uint64 array) before its step, i.e. the state
+    advanced by the golden gamma and passed through the two xor-shift-multiply
+    rounds and a final xor-shift.  Arithmetic modulo 2^64."""
+    with np.errstate(over="ignore"):  # the wrap modulo 2^64 is the definition
+        z = np.atleast_1d(np.asarray(state, dtype=np.uint64)) + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def input_noise(seed, step, rows, cols=36):
+    """Standard normal variates of the training-input noise of train step
+    `step` (the definition of lbm_mlp_set_noise): key K = seed * 0x100000001B3
+    + step (mod 2^64); feature c of dataset row i takes the SplitMix64 output
+    r for the state K ^ (64 i + c), u1 = ((r >> 40) + 1) / (2^24 + 1) in (0, 1),
+    u2 = ((r >> 16) mod 2^24) / 2^24 in [0, 1), and the Box-Muller variate
+    sqrt(-2 ln u1) cos(2 pi u2) (Box & Muller 1958), here in FP64.  Returns
+    [rows][cols]."""
+    key = (int(seed) * 0x100000001B3 + int(step)) % (1 << 64)
+    i = np.arange(rows, dtype=np.uint64)[:, None]
+    c = np.arange(cols, dtype=np.uint64)[None, :]
+    r = splitmix64_output(np.uint64(key) ^ (i * np.uint64(64) + c))
+    u1 = ((r >> np.uint64(40)).astype(np.float64) + 1.0) / 16777217.0
+    u2 = ((r >> np.uint64(16)) & np.uint64(0xFFFFFF)).astype(np.float64) / 16777216.0
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
+
+
 def adam(w, m, v, g, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     """One Adam update (step counts from 1); returns new (w, m, v)."""
     m = b1 * m + (1 - b1) * g

@@ -101,6 +101,29 @@ def test_adam_step_matches_reference():
     assert np.abs(w1 - ref_w).max() < 2e-6
 
 
+def test_training_noise_follows_its_definition():
+    """Train steps with input noise and learning rate 0 leave the network as
+    it is and return the loss on the noisy inputs: for each step k that loss
+    is the reference loss on x + amplitude * input_noise(seed, k), and not the
+    one with another step's noise."""
+    p = random_params(15, last=0.5)
+    rng = np.random.default_rng(16)
+    B, amp, seed = 64, 1.0, 11
+    x = rng.standard_normal((B, 36)).astype(np.float32).astype(np.float64)
+    t = (0.1 * rng.standard_normal((B, 3))).astype(np.float32).astype(np.float64)
+    net = lbm.Mlp(p)
+    net.set_noise(amp, seed)
+    xd, td = dev(x), dev(t)
+    for k in range(3):
+        got = net.train_step(xd, td, None, B, 0.0, want_loss=True)
+        ref = omlp.loss(p, x + amp * omlp.input_noise(seed, k, B), t)
+        other = omlp.loss(p, x + amp * omlp.input_noise(seed, k + 1, B), t)
+        note(f"  step {k}: loss {got:.6e}, reference {ref:.6e}, with the next step's noise {other:.6e}")
+        assert got == pytest.approx(ref, rel=2e-3)
+        assert abs(other - ref) > 20 * abs(got - ref)
+    assert np.array_equal(net.get_params(), p.astype(np.float32))
+
+
 def test_training_learns_a_teacher_network():
     """Targets from a fixed random network; 300 Adam steps on batches of 1024
     out of 8192 samples must cut the loss at least tenfold."""

@@ -70,3 +70,24 @@ def test_adam_first_step_moves_by_lr_times_sign():
     w, m, v = mlp.adam(np.zeros(4), np.zeros(4), np.zeros(4), g, 1, lr=1e-3)
     expect = -1e-3 * g / (np.abs(g) + 1e-8)
     assert np.allclose(w, expect, rtol=1e-12, atol=1e-18)
+
+
+def test_input_noise_generator_is_splitmix64_and_box_muller():
+    """The training-input noise: SplitMix64 outputs for the states 0, gamma,
+    2 gamma, 3 gamma are the published sequence of seed 0 (Steele, Lea &
+    Flood 2014), and the Box-Muller variates are standard normal (moments,
+    the two-sided 3-sigma tail, no correlation between steps or features)."""
+    gamma = 0x9E3779B97F4A7C15
+    states = np.array([(j * gamma) % (1 << 64) for j in range(4)], dtype=np.uint64)
+    assert [int(v) for v in mlp.splitmix64_output(states)] == [
+        0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
+    g0 = mlp.input_noise(11, 0, 20000)
+    g1 = mlp.input_noise(11, 1, 20000)
+    for g in (g0, g1):
+        assert g.shape == (20000, 36) and np.isfinite(g).all()
+        assert abs(g.mean()) < 0.01 and abs(g.var() - 1.0) < 0.01
+        assert abs(np.mean(g ** 3)) < 0.02 and abs(np.mean(g ** 4) - 3.0) < 0.05
+        assert 0.0022 < np.mean(np.abs(g) > 3.0) < 0.0032  # 2 (1 - Phi(3)) = 0.0027
+    assert abs(np.corrcoef(g0.ravel(), g1.ravel())[0, 1]) < 0.01
+    assert abs(np.corrcoef(g0[:, 0], g0[:, 1])[0, 1]) < 0.03
+    assert np.array_equal(mlp.input_noise(11, 0, 50), g0[:50])  # counter-based: rows do not depend on the count
