@@ -62,3 +62,18 @@ def test_an_explicit_interval_keeps_the_low_pass_time_constant():
         pass
     else:
         raise AssertionError("interval 0 accepted")
+
+
+def test_window_sits_inside_the_full_domain_around_the_same_cylinder():
+    for d in (20, 40, 80):
+        full = C.full_domain(d)
+        kw, ox, oy = C.window(d)
+        assert (full["nx"], full["ny"]) == (41 * d, 21 * d) and (kw["nx"], kw["ny"]) == (26 * d, 11 * d)
+        assert 0 <= ox and ox + kw["nx"] <= full["nx"] and 0 <= oy and oy + kw["ny"] <= full["ny"]
+        # the cylinder (centre at cx2/2, cy2/2) keeps its place relative to the window's inlet
+        assert kw["cx2"] == full["cx2"] - 2 * ox and kw["cy2"] == full["cy2"] - 2 * oy
+        assert kw["diameter"] == full["diameter"] == d
+        # boundary numbering of the closure: top row nodes 1 .. nx-2, bottom row nodes 1 .. nx-2,
+        # outlet rows 1 .. ny-2
+        assert C.n_boundary(kw) == 2 * (kw["nx"] - 2) + (kw["ny"] - 2)
+    assert C.n_boundary(C.window(40)[0]) == 2514
